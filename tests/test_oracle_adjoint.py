@@ -1,0 +1,76 @@
+"""Pins of the oracle's adjoint gradient (the FWI use of the forward engine,
+paper sec. 1 and sec. 4)."""
+import numpy as np
+
+from oracle import adjoint, direct, operator as op
+from paper_2110_15113_amd import workloads as wl
+
+
+def _setup(q=None, seed=21):
+    w = wl.small_random((9, 8, 10), npml=2, q=q, nsrc=2, seed=seed)
+    rec = [(3, 3, 3), (5, 4, 3), (6, 5, 6), (3, 5, 7)]
+    m0 = 1.0 / w.vel ** 2
+    return w, rec, m0
+
+
+def _J(w, rec, m, d_obs):
+    F = op.make_fields(w.vel, w.Q, w.omega, w.h, w.npml, weights_from=w.vel, m=m,
+                       c_ref=float(w.vel.max()))
+    A = op.assemble(F)
+    J, g, U, MU = adjoint.misfit_and_gradient(F, w.sources, rec, d_obs,
+                                              lambda b: direct.solve(A, F.shape, b))
+    return J, g
+
+
+def test_gradient_matches_finite_differences():
+    for q in (None, 40.0):
+        w, rec, m0 = _setup(q)
+        rng = np.random.default_rng(1)
+        d_obs = rng.normal(size=(2, len(rec))) * 1e-5 + 1j * rng.normal(size=(2, len(rec))) * 1e-5
+        J0, g = _J(w, rec, m0, d_obs)
+        for t in range(4):
+            dm = rng.normal(size=m0.shape) * m0
+            dm /= np.abs(dm).max()
+            eps = 1e-4 * np.abs(m0).max()
+            Jp, _ = _J(w, rec, m0 + eps * dm, d_obs)
+            Jm, _ = _J(w, rec, m0 - eps * dm, d_obs)
+            fd = (Jp - Jm) / (2 * eps)
+            an = float(np.sum(g * dm))
+            assert abs(fd - an) <= 1e-6 * abs(fd), (q, t, fd, an)
+
+
+def test_adjoint_identity():
+    """<P A^{-1} b, g> = <b, A^{-H} P^T g> with A^{-H} v = conj(A^{-1} conj(v))."""
+    w, rec, m0 = _setup(60.0)
+    F = op.make_fields(w.vel, w.Q, w.omega, w.h, w.npml)
+    A = op.assemble(F)
+    rng = np.random.default_rng(3)
+    b = rng.normal(size=(1,) + F.shape) + 1j * rng.normal(size=(1,) + F.shape)
+    g = rng.normal(size=(1, len(rec))) + 1j * rng.normal(size=(1, len(rec)))
+    lhs = np.vdot(g, adjoint.sample(direct.solve(A, F.shape, b), rec))
+    mu = np.conj(direct.solve(A, F.shape, np.conj(adjoint.spread(g, rec, F.shape))))
+    rhs = np.vdot(mu, b)
+    assert abs(lhs - rhs) <= 1e-11 * abs(lhs)
+
+
+def test_lumped_mass_reduces_to_pointwise_product():
+    """With wm0 = 1 (no off-diagonal mass) the gradient is
+    -omega^2 Re(q S sum_s conj(mu) u) per cell."""
+    w, rec, m0 = _setup(30.0)
+    F = op.make_fields(w.vel, w.Q, w.omega, w.h, w.npml)
+    F.w[..., 3] = 1.0
+    F.w[..., 4:] = 0.0
+    rng = np.random.default_rng(5)
+    U = rng.normal(size=(2,) + F.shape) + 1j * rng.normal(size=(2,) + F.shape)
+    MU = rng.normal(size=(2,) + F.shape) + 1j * rng.normal(size=(2,) + F.shape)
+    g = adjoint.gradient(F, U, MU)
+    ref = -np.real(F.omega ** 2 * F.qfac * F.S() * np.sum(np.conj(MU) * U, axis=0))
+    assert np.abs(g - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_sample_spread_are_transposes():
+    rec = [(1, 2, 3), (4, 0, 2), (1, 2, 3)]
+    rng = np.random.default_rng(0)
+    U = rng.normal(size=(2, 5, 6, 7)) + 1j * rng.normal(size=(2, 5, 6, 7))
+    G = rng.normal(size=(2, 3)) + 1j * rng.normal(size=(2, 3))
+    assert abs(np.vdot(G, adjoint.sample(U, rec)) - np.vdot(adjoint.spread(G, rec, (5, 6, 7)), U)) < 1e-12

@@ -1,0 +1,164 @@
+"""Pins of the oracle's direct solve, ORAS preconditioner and FGMRES
+(paper eq. 1.1, sec. 2.1, sec. 2.2)."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import direct, krylov, operator as op, oras, stencil_table as st
+from paper_2110_15113_amd import workloads as wl
+
+
+def _fields(w):
+    return op.make_fields(w.vel, w.Q, w.omega, w.h, w.npml)
+
+
+@pytest.mark.parametrize("shape,q", [((8, 7, 6), None), ((10, 9, 11), 50.0), ((12, 12, 12), 120.0)])
+def test_block_lu_matches_dense_bruteforce(shape, q):
+    w = wl.small_random(shape, npml=2, q=q, nsrc=3, seed=sum(shape))
+    F = _fields(w)
+    A = op.assemble(F)
+    b = op.point_sources(F, w.sources)
+    x = direct.solve(A, F.shape, b)
+    xd = np.linalg.solve(A.toarray(), b.reshape(3, -1).T).T.reshape(b.shape)
+    assert np.abs(x - xd).max() <= 1e-12 * np.abs(xd).max()
+
+
+def test_block_lu_matches_superlu_and_residual():
+    w = wl.small_random((20, 18, 16), npml=3, q=80, nsrc=2, seed=5)
+    F = _fields(w)
+    A = op.assemble(F)
+    b = op.point_sources(F, w.sources)
+    x = direct.solve(A, F.shape, b)
+    xs = spla.splu(A.tocsc()).solve(b.reshape(2, -1).T).T.reshape(b.shape)
+    assert np.abs(x - xs).max() <= 1e-10 * np.abs(xs).max()
+    r = A @ x.reshape(2, -1).T - b.reshape(2, -1).T
+    assert np.linalg.norm(r) <= 1e-12 * np.linalg.norm(b)
+
+
+def test_reciprocity():
+    """A = A^T, so the field of source s read at r equals the field of r read
+    at s (heterogeneous model with Q and PML)."""
+    w = wl.small_random((14, 13, 12), npml=3, q=70, nsrc=2, seed=9)
+    F = _fields(w)
+    A = op.assemble(F)
+    b = op.point_sources(F, w.sources)
+    u = direct.solve(A, F.shape, b)
+    (i0, j0, k0), (i1, j1, k1) = w.sources
+    a = u[0, k1, j1, i1]
+    bb = u[1, k0, j0, i0]
+    assert abs(a - bb) <= 1e-10 * abs(a)
+
+
+@pytest.mark.parametrize("Q", [None, 50.0])
+def test_greens_function_homogeneous(Q):
+    """Homogeneous medium, G = 8: away from the source and inside the physical
+    region the field equals -h^3 e^{ik r} / (4 pi r) / mu(k h), where mu is the
+    stencil's mass symbol on the wave sphere (a point source is not mass
+    weighted, so the far field is scaled by 1 / mu), k = omega / c~ with
+    attenuation."""
+    n, c, h, f, npml = 32, 2000.0, 25.0, 10.0, 8
+    vel = np.full((n, n, n), c)
+    Qa = None if Q is None else np.full_like(vel, Q)
+    F = op.make_fields(vel, Qa, 2 * np.pi * f, h, npml)
+    A = op.assemble(F)
+    b = op.point_sources(F, [(16, 16, 16)])[0]
+    M = oras.ORAS(F, (2, 2, 2), 2)
+    u, it, ok, _ = krylov.fgmres(lambda v: A @ v,
+                                 lambda v: M.apply(v.reshape(F.shape)).reshape(-1),
+                                 b.reshape(-1), 1e-10, 30, 200)
+    assert ok
+    u = u.reshape(F.shape)
+    kk, jj, ii = np.meshgrid(*[np.arange(n)] * 3, indexing="ij")
+    r = h * np.sqrt((ii - 16) ** 2 + (jj - 16) ** 2 + (kk - 16) ** 2)
+    k = 2 * np.pi * f / c * (1.0 if Q is None else (1 + 0.5j / Q))
+    rr = np.maximum(r, h)
+    g = -h ** 3 * np.exp(1j * k * rr) / (4 * np.pi * rr)
+    _, mu = st.lam_mu(F.w[16, 16, 16], (2 * np.pi * f / c * h) * np.array([1.0, 0.0, 0.0]))
+    phys = ((ii >= npml) & (ii < n - npml) & (jj >= npml) & (jj < n - npml)
+            & (kk >= npml) & (kk < n - npml))
+    m = phys & (r >= 4 * h)
+    rel = np.abs(u * mu - g)[m] / np.abs(g)[m]
+    assert rel.max() < 1e-2, rel.max()
+
+
+def test_oras_one_subdomain_is_exact():
+    w = wl.small_random((10, 11, 12), npml=2, q=90)
+    F = _fields(w)
+    A = op.assemble(F)
+    M = oras.ORAS(F, (1, 1, 1), 2)
+    v = np.random.default_rng(0).normal(size=F.shape) + 1j
+    x = M.apply(v)
+    assert np.linalg.norm(A @ x.reshape(-1) - v.reshape(-1)) <= 1e-12 * np.linalg.norm(v)
+
+
+def test_partition_is_partition_of_unity():
+    subs = oras.partition((17, 13, 11), (3, 2, 4), 2)
+    cover = np.zeros((11, 13, 17), dtype=int)
+    for s in subs:
+        cover[s.olo[2]:s.ohi[2], s.olo[1]:s.ohi[1], s.olo[0]:s.ohi[0]] += 1
+        for a, n in enumerate((17, 13, 11)):
+            assert s.lo[a] == max(0, s.olo[a] - 2) and s.hi[a] == min(n, s.ohi[a] + 2)
+    assert np.all(cover == 1)
+
+
+def test_oras_stationary_iteration_converges_to_direct():
+    w = wl.small_random((16, 16, 16), npml=3, q=100, seed=3)
+    F = _fields(w)
+    A = op.assemble(F)
+    b = op.point_sources(F, w.sources)[0]
+    u = direct.solve(A, F.shape, b)
+    M = oras.ORAS(F, (2, 2, 2), 2)
+    x = np.zeros_like(b)
+    errs = []
+    for _ in range(40):
+        x = x + M.apply(b - op.apply_coeffs(op.row_coeffs(F), x))
+        errs.append(np.linalg.norm(x - u) / np.linalg.norm(u))
+    assert errs[-1] < 1e-10, errs[-5:]
+
+
+def test_fgmres_config1_matches_direct():
+    c = wl.config1()
+    F = _fields(c)
+    A = op.assemble(F)
+    b = op.point_sources(F, c.sources)[0]
+    u = direct.solve(A, F.shape, b)
+    M = oras.ORAS(F, c.parts, c.overlap)
+    x, it, ok, hist = krylov.fgmres(lambda v: A @ v,
+                                    lambda v: M.apply(v.reshape(F.shape)).reshape(-1),
+                                    b.reshape(-1), c.tol, c.restart, c.maxit)
+    assert ok and it < 40
+    assert np.linalg.norm(A @ x - b.reshape(-1)) <= c.tol * np.linalg.norm(b)
+    assert np.linalg.norm(x - u.reshape(-1)) <= 1e-6 * np.linalg.norm(u)
+
+
+def test_fgmres_one_subdomain_one_iteration_and_restart():
+    w = wl.small_random((9, 9, 9), npml=2, q=60, nsrc=1)
+    F = _fields(w)
+    A = op.assemble(F)
+    M = oras.ORAS(F, (1, 1, 1), 1)
+    b = op.point_sources(F, w.sources)[0].reshape(-1)
+    x, it, ok, _ = krylov.fgmres(lambda v: A @ v, lambda v: M.apply(v.reshape(F.shape)).reshape(-1),
+                                 b, 1e-12, 30, 30)
+    assert ok and it == 1
+    # restart length 2 with an ORAS of 8 subdomains still converges
+    M8 = oras.ORAS(F, (2, 2, 2), 1)
+    x2, it2, ok2, _ = krylov.fgmres(lambda v: A @ v, lambda v: M8.apply(v.reshape(F.shape)).reshape(-1),
+                                    b, 1e-10, 2, 400)
+    assert ok2
+    assert np.linalg.norm(x2 - x) <= 1e-8 * np.linalg.norm(x)
+
+
+def test_pseudo_block_equals_single_and_zero_column():
+    w = wl.small_random((10, 10, 10), npml=2, q=60, nsrc=2)
+    F = _fields(w)
+    A = op.assemble(F)
+    M = oras.ORAS(F, (2, 1, 2), 2)
+    b = op.point_sources(F, w.sources).reshape(2, -1)
+    B = np.vstack([b, np.zeros_like(b[:1])])
+    Aop = lambda v: A @ v
+    Mop = lambda v: M.apply(v.reshape(F.shape)).reshape(-1)
+    X, its, conv = krylov.fgmres_block(Aop, Mop, B, 1e-10, 30, 200)
+    for c in range(2):
+        x, it, ok, _ = krylov.fgmres(Aop, Mop, b[c], 1e-10, 30, 200)
+        assert np.abs(X[c] - x).max() <= 1e-14 * np.abs(x).max()
+    assert conv[2] and its[2] == 0 and not np.any(X[2])
