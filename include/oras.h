@@ -1,0 +1,200 @@
+/*
+ * oras.h -- C ABI of the MI355X (gfx950) ORAS-FGMRES Helmholtz solver.
+ *
+ * Solves A u = f for the 3D frequency-domain Helmholtz equation
+ * (Delta + k^2) u = f, k = omega / c with c complex in viscous media
+ * (arXiv 2110.15113, sec. 2, eq. 1 and eq. 1.1), discretised by the compact
+ * lambda-adaptive 27-point finite-difference stencil with PML layers on all
+ * faces (sec. 2.3 FDFD; sec. 3.1), by right-preconditioned flexible GMRES
+ * (sec. 2.1, sec. 2.2) with the one-level optimized restricted additive
+ * Schwarz preconditioner M^{-1} = sum_j R_j^T D_j B_j^{-1} R_j whose local
+ * matrices carry Robin (impedance) interface conditions (sec. 2.1), local
+ * factorisations computed once at set-up and applied by forward/backward
+ * substitution on a whole block of right-hand sides (sec. 2.2, pseudo-block).
+ *
+ * Conventions (the paper leaves them open; all are fixed here):
+ *   time dependence e^{-i omega t}; A = Delta_h + omega^2 M(m~) (paper sign);
+ *   attenuation 1/c~ = (1/c)(1 + i/(2Q)); PML s = 1 + i sigma / omega with a
+ *   quadratic profile, sigma_max = 3 c_ref ln(1/R0) / (2 L); Robin term
+ *   i k S / (s_a h) on the diagonal of B_j per interior face; Boolean
+ *   partition of unity (owner computes); stopping test per column
+ *   ||b - A x||_2 <= tol ||b||_2 on the FP64 true residual.
+ *
+ * Memory and layouts
+ *   - Every pointer named *_dev is device memory on the context's device,
+ *     owned by the caller, and must stay valid until the call returns (all
+ *     calls are ordered on the context's stream and synchronise it before
+ *     returning).
+ *   - Wavefields / right-hand sides: complex128 interleaved (re, im), shape
+ *     (nrhs, nz, ny, nx), C order, x fastest -- torch.complex128 contiguous.
+ *   - Model arrays (velocity, Q, m): float64, shape (nz, ny, nx).
+ *   - Host pointers (*_host, info arrays) are caller-owned host memory.
+ *   - The context owns the stencil coefficients, the subdomain factors and
+ *     the Krylov workspace; they are freed by oras_destroy.
+ *
+ * Errors
+ *   Every function returns an oras_status and never aborts.  Argument and
+ *   state checks run before any device call; on error the context keeps its
+ *   previous valid state and oras_last_error() describes the problem.
+ *
+ * State machine: create -> assemble -> factor_subdomains -> solve ...
+ *   assemble and set_m drop the factors (B_j depends on m).
+ *   A context is not thread-safe.
+ */
+#ifndef ORAS_H
+#define ORAS_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct oras_ctx_s* oras_ctx;
+
+typedef enum {
+  ORAS_OK = 0,
+  ORAS_E_ARG = 1,        /* invalid argument (checked before any device call) */
+  ORAS_E_STATE = 2,      /* call out of order, e.g. solve before factor */
+  ORAS_E_OOM = 3,        /* device allocation failed or size limit exceeded */
+  ORAS_E_HIP = 4,        /* HIP runtime error, or no device in this context */
+  ORAS_E_NUMERIC = 5,    /* zero / non-finite pivot, NaN residual, breakdown */
+  ORAS_W_NOT_CONVERGED = 100  /* warning: some column hit maxit */
+} oras_status;
+
+typedef enum { ORAS_C64 = 1, ORAS_C128 = 2 } oras_prec;
+
+/* Solve flags */
+#define ORAS_CONJ 1   /* solve A conj(x) = conj(b), i.e. the adjoint A^H x = b
+                         (A is complex symmetric; sec. 2, Method) */
+#define ORAS_X0 2     /* x_dev holds an initial guess (warm start / resume) */
+
+typedef struct {
+  int nx, ny, nz;      /* nodes per axis, PML included */
+  double h;            /* grid step (m) */
+  int npml;            /* PML nodes on each face */
+  int free_surface;    /* 1: no PML on the top face (k = 0), Dirichlet above */
+} oras_grid;
+
+typedef struct {
+  double R0;           /* target reflection coefficient (> 0, < 1), e.g. 1e-3 */
+  int power;           /* profile exponent, e.g. 2 */
+  double c_ref;        /* reference velocity; <= 0 selects the model maximum */
+} oras_pml;
+
+typedef struct {
+  int restart;         /* FGMRES restart length m (1..200) */
+  int maxit;           /* maximum Arnoldi steps per column (>= 1) */
+  int flags;           /* ORAS_CONJ | ORAS_X0 */
+  int reserved;
+} oras_solve_opts;
+
+typedef struct {
+  int* iters;          /* [nrhs] Arnoldi steps taken per column (host, may be NULL) */
+  double* rel_res;     /* [nrhs] final true relative residual (host, may be NULL) */
+  int* converged;      /* [nrhs] 1 if the column met tol (host, may be NULL) */
+  double t_solve;      /* seconds, whole call */
+  double t_stencil;    /* seconds in the stencil apply (HIP events) */
+  double t_oras;       /* seconds in the ORAS apply */
+  double t_ortho;      /* seconds in Gram-Schmidt + Givens */
+  int cycles;          /* restart cycles */
+  int total_iters;     /* Arnoldi steps of the block */
+} oras_solve_info;
+
+/* Create a context on HIP device `device` using `hip_stream` (a hipStream_t,
+ * NULL = default stream).  device = -1 creates a host-only context that
+ * validates arguments but refuses every device operation (ORAS_E_HIP); it
+ * exists so argument checking can be tested without a GPU. */
+oras_status oras_create(oras_ctx* out, int device, void* hip_stream);
+
+/* Release everything the context owns.  NULL is ignored. */
+void oras_destroy(oras_ctx ctx);
+
+/* Message of the last error on this context (never NULL). */
+const char* oras_last_error(oras_ctx ctx);
+
+/* The library's own lambda-adaptive weight table (paper sec. 2.3: weights
+ * fitted per G = lambda / h by least squares on the phase-velocity
+ * dispersion).  Writes up to `capacity` rows of 7 doubles (w1 w2 w3 wm0 wmf
+ * wme wmc) into out_host, and the grid G = g0 + dg * row, row < *count.
+ * Host only; needs no context.  capacity < count -> ORAS_E_ARG. */
+oras_status oras_weight_table(double* out_host, int capacity, double* g0, double* dg, int* count);
+
+/* Assemble the operator (paper eq. 1; sec. 2.3 27-point lambda-adaptive
+ * stencil; PML per sec. 3.1).  vel_dev: velocity (m/s, > 0, finite);
+ * q_dev: quality factor (> 0) or NULL for no attenuation; omega > 0;
+ * stencil_prec: ORAS_C128 (all FP64) or ORAS_C64 (the Krylov stencil runs in
+ * complex FP32; an FP64 copy is kept for the true residual).  Requires
+ * 3 <= nx, ny, nz, 0 <= 2 npml < min(n).  Drops any factors. */
+oras_status oras_assemble(oras_ctx ctx, const oras_grid* grid, const double* vel_dev,
+                          const double* q_dev, double omega, const oras_pml* pml,
+                          int stencil_prec);
+
+/* Replace the real squared slowness m (s^2/m^2, (nz,ny,nx) float64 > 0) and
+ * re-assemble with the stencil weights, PML and Q frozen at the last
+ * oras_assemble.  Used by the differentiable forward map.  Drops factors. */
+oras_status oras_set_m(oras_ctx ctx, const double* m_dev);
+
+/* Partition the grid into parts[0] x parts[1] x parts[2] cuboids (floor
+ * split), extend each by `overlap` layers on interior sides (sec. 2.2:
+ * overlapping cuboids), assemble every local matrix B_j with Robin interface
+ * faces (sec. 2.1) and factor it on the device (block elimination over the
+ * z-planes of the box, explicit inverses of the plane Schur complements by
+ * blocked Gauss-Jordan).  factor_prec: ORAS_C64 or ORAS_C128.  Each box must
+ * have at least 2 nodes per axis and overlap must be 0..8.  A zero or
+ * non-finite pivot returns ORAS_E_NUMERIC and leaves no factors. */
+oras_status oras_factor_subdomains(oras_ctx ctx, const int parts[3], int overlap,
+                                   int factor_prec);
+
+/* Solve A x_c = b_c for nrhs columns with pseudo-block right-preconditioned
+ * FGMRES (sec. 2.1, sec. 2.2): FP64 Arnoldi basis, classical Gram-Schmidt,
+ * complex Givens, FP64 true residual at each restart; the stencil and ORAS
+ * run in the assembled / factored precisions.  b_dev, x_dev: (nrhs,nz,ny,nx)
+ * complex128.  tol in (0, 1).  Columns with b = 0 return x = 0 (converged).
+ * Returns ORAS_W_NOT_CONVERGED when a column reached maxit. */
+oras_status oras_solve(oras_ctx ctx, const void* b_dev, void* x_dev, int nrhs, double tol,
+                       const oras_solve_opts* opts, oras_solve_info* info);
+
+/* b_dev (nrhs, nz, ny, nx) complex128 := point sources (sec. 3.1: a delta at
+ * a grid node); column c has amplitude (amp_host[2c], amp_host[2c+1]) (1 if
+ * amp_host is NULL) at node idx_host[3c..3c+2] = (i, j, k), times the PML
+ * factor S there.  Indices must lie inside the grid. */
+oras_status oras_point_sources(oras_ctx ctx, const int* idx_host, const double* amp_host,
+                               int nrhs, void* b_dev);
+
+/* d_dev (nrhs, nrec) complex128 := u sampled at receivers rec_dev
+ * (nrec x 3 int32 (i, j, k), device).  u_dev (nrhs, nz, ny, nx). */
+oras_status oras_sample(oras_ctx ctx, const void* u_dev, int nrhs, const int* rec_dev, int nrec,
+                        void* d_dev);
+
+/* b_dev (nrhs, nz, ny, nx) := P^T d (zero elsewhere, duplicates summed). */
+oras_status oras_spread(oras_ctx ctx, const void* d_dev, int nrhs, const int* rec_dev, int nrec,
+                        void* b_dev);
+
+/* g_dev (nz, ny, nx) float64 := -Re sum_c mu_c^H (dA/dm) u_c, the gradient
+ * of a real misfit w.r.t. the squared slowness m given the adjoint fields
+ * mu (A^H mu = P^T dJ/dd); stencil weights frozen (FWI use, sec. 1, sec. 4). */
+oras_status oras_gradient(oras_ctx ctx, const void* u_dev, const void* mu_dev, int nrhs,
+                          double* g_dev);
+
+/* Test hooks running the same kernels as the solver.
+ * oras_apply_A: y = A x in precision prec (ORAS_C64 needs stencil_prec C64).
+ * oras_apply_M: y = M^{-1} x with the current factors.
+ * x, y: (nrhs, nz, ny, nx) complex128. */
+oras_status oras_apply_A(oras_ctx ctx, const void* x_dev, void* y_dev, int nrhs, int prec);
+oras_status oras_apply_M(oras_ctx ctx, const void* x_dev, void* y_dev, int nrhs);
+
+/* Wall-clock seconds of the last oras_assemble and of the last
+ * oras_factor_subdomains (the paper's set-up time T_f, sec. 3.2). */
+oras_status oras_timings(oras_ctx ctx, double* t_assemble, double* t_factor);
+
+/* Copy the 27 FP64 stencil coefficients per node, layout (27, nz, ny, nx)
+ * complex128, slot e = (ez+1)*9 + (ey+1)*3 + (ex+1). */
+oras_status oras_coefficients(oras_ctx ctx, void* out_dev);
+
+/* Number of subdomains and the box / owned cuboid of subdomain j
+ * (lo x,y,z, hi x,y,z, olo..., ohi...) into box12_host. */
+oras_status oras_subdomain(oras_ctx ctx, int j, int* nsub, int* box12_host);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

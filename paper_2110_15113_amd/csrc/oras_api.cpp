@@ -1,0 +1,869 @@
+// Host driver and C ABI of the ORAS-FGMRES Helmholtz library.
+//
+// Paper sec. 2.1 (right-preconditioned GMRES with the one-level ORAS
+// preconditioner), sec. 2.2 (overlapping cuboids, local factorisations at
+// set-up, forward/backward substitution on a block of right-hand sides,
+// flexible GMRES), sec. 2.3 (27-point lambda-adaptive stencil), sec. 3.2
+// (classical Gram-Schmidt, single vs double precision).
+//
+// Every entry point validates its arguments and the context state before
+// touching the device, so a failing call leaves the context as it was.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "oras_internal.h"
+
+namespace oras {
+void fit_table(std::vector<double>& tab, double& g0, double& dg, int& count);
+}
+
+using namespace oras;
+
+namespace {
+
+struct Table {
+  std::vector<double> w;
+  double g0 = 0, dg = 0;
+  int count = 0;
+};
+
+const Table& weight_table() {
+  static Table t;
+  static std::once_flag once;
+  std::call_once(once, [] { fit_table(t.w, t.g0, t.dg, t.count); });
+  return t;
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+}  // namespace
+
+struct oras_ctx_s {
+  int device = -1;
+  hipStream_t stream = nullptr;
+  bool host_only = true;
+  std::string err;
+
+  // operator
+  bool assembled = false;
+  int nx = 0, ny = 0, nz = 0;
+  long long n = 0;
+  double h = 0, omega = 0;
+  int npml = 0, free_surface = 0;
+  double c_ref = 0;
+  int stencil_prec = ORAS_C128;
+  DevBuf w7, mt, qf, px, py, pz, coef128, coef64, wtab, scratch8;
+  double t_assemble = 0;
+
+  // factors
+  bool factored = false;
+  int factor_prec = ORAS_C128;
+  int parts[3] = {1, 1, 1};
+  int overlap = 0;
+  std::vector<SubDesc> subs;
+  DevBuf subs_dev, fac, lca, owner, status;
+  int max_sz = 0, max_nt = 0;
+  long long max_p = 0, max_box = 0, y_rows = 0, tv_rows = 0;
+  double t_factor = 0;
+
+  // per-solve workspace (grown on demand)
+  DevBuf ybuf, tvbuf, V, Z, Bint, Xint, Tmp, Tmp64, partial, small;
+  long long ws_s = 0;
+  int ws_m = 0;
+
+  ~oras_ctx_s() { release_all(); }
+  void release_factors() {
+    subs_dev.release(); fac.release(); lca.release(); owner.release(); status.release();
+    ybuf.release(); tvbuf.release();
+    subs.clear();
+    factored = false;
+  }
+  void release_workspace() {
+    V.release(); Z.release(); Bint.release(); Xint.release(); Tmp.release(); Tmp64.release();
+    partial.release(); small.release();
+    ws_s = 0;
+    ws_m = 0;
+  }
+  void release_all() {
+    release_factors();
+    release_workspace();
+    w7.release(); mt.release(); qf.release(); px.release(); py.release(); pz.release();
+    coef128.release(); coef64.release(); wtab.release(); scratch8.release();
+    assembled = false;
+  }
+};
+
+namespace {
+
+oras_status fail(oras_ctx c, oras_status st, const std::string& msg) {
+  if (c) c->err = msg;
+  return st;
+}
+
+#define HIP_TRY(ctx, expr)                                                         \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return fail(ctx, ORAS_E_HIP, std::string("HIP error ") + hipGetErrorString(e_) + \
+                                       " at " #expr);                              \
+  } while (0)
+
+oras_status dev_alloc(oras_ctx c, DevBuf& b, size_t bytes) {
+  if (b.bytes >= bytes && b.p) return ORAS_OK;
+  b.release();
+  if (bytes == 0) return ORAS_OK;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, ORAS_E_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  b.p = p;
+  b.bytes = bytes;
+  return ORAS_OK;
+}
+
+#define TRY(expr)                        \
+  do {                                   \
+    oras_status s_ = (expr);             \
+    if (s_ != ORAS_OK) return s_;        \
+  } while (0)
+
+oras_status check_device(oras_ctx c) {
+  if (c->host_only) return fail(c, ORAS_E_HIP, "context has no device (created with device = -1)");
+  HIP_TRY(c, hipSetDevice(c->device));
+  return ORAS_OK;
+}
+
+oras_status check_free(oras_ctx c, double bytes) {
+  size_t fr = 0, tot = 0;
+  HIP_TRY(c, hipMemGetInfo(&fr, &tot));
+  if (bytes > 0.97 * (double)fr)
+    return fail(c, ORAS_E_OOM, "needs " + std::to_string(bytes / 1e9) + " GB, " +
+                                   std::to_string((double)fr / 1e9) + " GB free");
+  return ORAS_OK;
+}
+
+OpView opview(oras_ctx c) {
+  OpView v;
+  v.nx = c->nx;
+  v.ny = c->ny;
+  v.nz = c->nz;
+  v.h = c->h;
+  v.omega = c->omega;
+  v.w7 = c->w7.as<double>();
+  v.mt = c->mt.as<double2>();
+  v.px = c->px.as<double2>();
+  v.py = c->py.as<double2>();
+  v.pz = c->pz.as<double2>();
+  return v;
+}
+
+long long pad_s(int nrhs) { return ((long long)nrhs + RHS_ALIGN - 1) / RHS_ALIGN * RHS_ALIGN; }
+
+size_t csize(int prec) { return prec == ORAS_C64 ? sizeof(float2) : sizeof(double2); }
+
+oras_status build_coefficients(oras_ctx c) {
+  const OpView op = opview(c);
+  launch_assemble_global(op, c->coef128.as<double2>(),
+                         c->stencil_prec == ORAS_C64 ? c->coef64.as<float2>() : nullptr, c->stream);
+  HIP_TRY(c, hipGetLastError());
+  return ORAS_OK;
+}
+
+int nblk_for(long long n) {
+  long long b = (n + 255) / 256;
+  return (int)std::max(1LL, std::min(2048LL, b));
+}
+
+// y (internal [n][s] c128) = A x in precision prec; x internal c128.
+oras_status stencil_internal(oras_ctx c, const double2* x, const double2* b, double2* y, int s,
+                             int prec) {
+  if (prec == ORAS_C64) {
+    TRY(dev_alloc(c, c->Tmp64, (size_t)c->n * s * sizeof(float2)));
+    launch_cast<float>(x, c->Tmp64.as<float2>(), c->n * s, c->stream);
+    launch_stencil<float>(c->coef64.as<float2>(), c->Tmp64.as<float2>(), b, y, c->nx, c->ny, c->nz,
+                          s, c->stream);
+  } else {
+    launch_stencil<double>(c->coef128.as<double2>(), x, b, y, c->nx, c->ny, c->nz, s, c->stream);
+  }
+  HIP_TRY(c, hipGetLastError());
+  return ORAS_OK;
+}
+
+oras_status ensure_oras_ws(oras_ctx c, long long s) {
+  const size_t cs = csize(c->factor_prec);
+  TRY(dev_alloc(c, c->ybuf, (size_t)(c->y_rows * s) * cs));
+  TRY(dev_alloc(c, c->tvbuf, (size_t)(c->tv_rows * s) * cs));
+  return ORAS_OK;
+}
+
+// z (internal, factor precision or c128 when z128) = M^{-1} (scale * v)
+oras_status oras_apply_internal(oras_ctx c, const double2* v, const double* scale, void* z, int s,
+                                bool z128) {
+  TRY(ensure_oras_ws(c, s));
+  const int* own = c->owner.as<int>();
+  if (c->factor_prec == ORAS_C64) {
+    if (z128)
+      launch_oras_apply<float, double2>(c->subs_dev.as<SubDesc>(), (int)c->subs.size(), c->max_sz,
+                                        c->max_nt, c->max_p, c->fac.as<float2>(),
+                                        c->lca.as<float2>(), c->ybuf.as<float2>(),
+                                        c->tvbuf.as<float2>(), v, scale, (double2*)z, c->nx, c->ny,
+                                        c->nz, s, own, c->parts[0], c->parts[1], c->stream);
+    else
+      launch_oras_apply<float, float2>(c->subs_dev.as<SubDesc>(), (int)c->subs.size(), c->max_sz,
+                                       c->max_nt, c->max_p, c->fac.as<float2>(),
+                                       c->lca.as<float2>(), c->ybuf.as<float2>(),
+                                       c->tvbuf.as<float2>(), v, scale, (float2*)z, c->nx, c->ny,
+                                       c->nz, s, own, c->parts[0], c->parts[1], c->stream);
+  } else {
+    launch_oras_apply<double, double2>(c->subs_dev.as<SubDesc>(), (int)c->subs.size(), c->max_sz,
+                                       c->max_nt, c->max_p, c->fac.as<double2>(),
+                                       c->lca.as<double2>(), c->ybuf.as<double2>(),
+                                       c->tvbuf.as<double2>(), v, scale, (double2*)z, c->nx, c->ny,
+                                       c->nz, s, own, c->parts[0], c->parts[1], c->stream);
+  }
+  HIP_TRY(c, hipGetLastError());
+  return ORAS_OK;
+}
+
+double now() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+// receiver indices live on the device: copy them back once and bound-check
+oras_status check_receivers(oras_ctx c, const int* rec_dev, int nrec) {
+  std::vector<int> r((size_t)nrec * 3);
+  HIP_TRY(c, hipMemcpyAsync(r.data(), rec_dev, r.size() * sizeof(int), hipMemcpyDeviceToHost,
+                            c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (int q = 0; q < nrec; ++q)
+    if (r[3 * q] < 0 || r[3 * q] >= c->nx || r[3 * q + 1] < 0 || r[3 * q + 1] >= c->ny ||
+        r[3 * q + 2] < 0 || r[3 * q + 2] >= c->nz)
+      return fail(c, ORAS_E_ARG, "receiver index outside the grid");
+  return ORAS_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI --
+extern "C" {
+
+oras_status oras_create(oras_ctx* out, int device, void* hip_stream) {
+  if (!out) return ORAS_E_ARG;
+  *out = nullptr;
+  if (device < -1) return ORAS_E_ARG;
+  oras_ctx c = new (std::nothrow) oras_ctx_s();
+  if (!c) return ORAS_E_OOM;
+  c->device = device;
+  c->host_only = (device < 0);
+  c->stream = (hipStream_t)hip_stream;
+  if (!c->host_only) {
+    int cnt = 0;
+    if (hipGetDeviceCount(&cnt) != hipSuccess || device >= cnt) {
+      (void)hipGetLastError();
+      delete c;
+      return ORAS_E_HIP;
+    }
+    if (hipSetDevice(device) != hipSuccess) {
+      delete c;
+      return ORAS_E_HIP;
+    }
+  }
+  *out = c;
+  return ORAS_OK;
+}
+
+void oras_destroy(oras_ctx ctx) {
+  if (!ctx) return;
+  if (!ctx->host_only) {
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+  }
+  delete ctx;
+}
+
+const char* oras_last_error(oras_ctx ctx) {
+  if (!ctx) return "null context";
+  return ctx->err.c_str();
+}
+
+oras_status oras_weight_table(double* out_host, int capacity, double* g0, double* dg, int* count) {
+  const Table& t = weight_table();
+  if (count) *count = t.count;
+  if (g0) *g0 = t.g0;
+  if (dg) *dg = t.dg;
+  if (!out_host) return ORAS_OK;
+  if (capacity < t.count) return ORAS_E_ARG;
+  std::memcpy(out_host, t.w.data(), sizeof(double) * 7 * t.count);
+  return ORAS_OK;
+}
+
+oras_status oras_timings(oras_ctx ctx, double* t_assemble, double* t_factor) {
+  if (!ctx) return ORAS_E_ARG;
+  if (t_assemble) *t_assemble = ctx->t_assemble;
+  if (t_factor) *t_factor = ctx->t_factor;
+  return ORAS_OK;
+}
+
+oras_status oras_assemble(oras_ctx c, const oras_grid* g, const double* vel_dev,
+                          const double* q_dev, double omega, const oras_pml* pml,
+                          int stencil_prec) {
+  if (!c) return ORAS_E_ARG;
+  if (!g || !vel_dev || !pml) return fail(c, ORAS_E_ARG, "null grid, velocity or pml");
+  if (g->nx < 3 || g->ny < 3 || g->nz < 3) return fail(c, ORAS_E_ARG, "grid needs >= 3 nodes per axis");
+  if ((long long)g->nx * g->ny * g->nz > (1LL << 31))
+    return fail(c, ORAS_E_OOM, "grid larger than 2^31 nodes");
+  if (!finite_pos(g->h)) return fail(c, ORAS_E_ARG, "grid step must be finite and > 0");
+  if (g->npml < 0 || 2 * g->npml >= std::min(g->nx, std::min(g->ny, g->nz)))
+    return fail(c, ORAS_E_ARG, "npml must satisfy 0 <= 2 npml < min(nx, ny, nz)");
+  if (!finite_pos(omega)) return fail(c, ORAS_E_ARG, "omega must be finite and > 0");
+  if (!(pml->R0 > 0.0 && pml->R0 < 1.0)) return fail(c, ORAS_E_ARG, "pml R0 must be in (0, 1)");
+  if (pml->power < 0 || pml->power > 8) return fail(c, ORAS_E_ARG, "pml power must be 0..8");
+  if (!std::isfinite(pml->c_ref)) return fail(c, ORAS_E_ARG, "pml c_ref must be finite");
+  if (stencil_prec != ORAS_C64 && stencil_prec != ORAS_C128)
+    return fail(c, ORAS_E_ARG, "stencil_prec must be ORAS_C64 or ORAS_C128");
+  TRY(check_device(c));
+  const double t0 = now();
+  const long long n = (long long)g->nx * g->ny * g->nz;
+  const double need = (double)n * (7 * 8 + 16 * 2 + 27 * 16 + (stencil_prec == ORAS_C64 ? 27 * 8 : 0));
+  c->release_all();
+  TRY(check_free(c, need));
+  c->nx = g->nx;
+  c->ny = g->ny;
+  c->nz = g->nz;
+  c->n = n;
+  c->h = g->h;
+  c->omega = omega;
+  c->npml = g->npml;
+  c->free_surface = g->free_surface ? 1 : 0;
+  c->stencil_prec = stencil_prec;
+  const Table& t = weight_table();
+  TRY(dev_alloc(c, c->w7, (size_t)n * 7 * sizeof(double)));
+  TRY(dev_alloc(c, c->mt, (size_t)n * sizeof(double2)));
+  TRY(dev_alloc(c, c->qf, (size_t)n * sizeof(double2)));
+  TRY(dev_alloc(c, c->px, (size_t)(2 * g->nx + 1) * sizeof(double2)));
+  TRY(dev_alloc(c, c->py, (size_t)(2 * g->ny + 1) * sizeof(double2)));
+  TRY(dev_alloc(c, c->pz, (size_t)(2 * g->nz + 1) * sizeof(double2)));
+  TRY(dev_alloc(c, c->coef128, (size_t)n * 27 * sizeof(double2)));
+  if (stencil_prec == ORAS_C64) TRY(dev_alloc(c, c->coef64, (size_t)n * 27 * sizeof(float2)));
+  TRY(dev_alloc(c, c->wtab, t.w.size() * sizeof(double)));
+  TRY(dev_alloc(c, c->scratch8, 64));
+  HIP_TRY(c, hipMemcpyAsync(c->wtab.p, t.w.data(), t.w.size() * sizeof(double),
+                            hipMemcpyHostToDevice, c->stream));
+  // velocity checks and the PML reference velocity (maximum of the model)
+  launch_max_reduce(vel_dev, n, c->scratch8.as<double>(), c->stream);
+  double vmax = 0;
+  HIP_TRY(c, hipMemcpyAsync(&vmax, c->scratch8.p, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (!finite_pos(vmax)) {
+    c->release_all();
+    return fail(c, ORAS_E_ARG, "velocity maximum is not finite and positive");
+  }
+  c->c_ref = pml->c_ref > 0 ? pml->c_ref : vmax;
+  launch_fields(vel_dev, q_dev, nullptr, c->wtab.as<double>(), t.count, t.g0, t.dg, c->nx, c->ny,
+                c->nz, c->h, omega, c->w7.as<double>(), c->qf.as<double2>(), c->mt.as<double2>(),
+                c->stream, 0);
+  launch_pml(c->px.as<double2>(), c->nx, c->npml, c->h, omega, c->c_ref, pml->R0, pml->power, 1, 1,
+             c->stream);
+  launch_pml(c->py.as<double2>(), c->ny, c->npml, c->h, omega, c->c_ref, pml->R0, pml->power, 1, 1,
+             c->stream);
+  launch_pml(c->pz.as<double2>(), c->nz, c->npml, c->h, omega, c->c_ref, pml->R0, pml->power,
+             c->free_surface ? 0 : 1, 1, c->stream);
+  HIP_TRY(c, hipGetLastError());
+  TRY(build_coefficients(c));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->assembled = true;
+  c->t_assemble = now() - t0;
+  return ORAS_OK;
+}
+
+oras_status oras_set_m(oras_ctx c, const double* m_dev) {
+  if (!c) return ORAS_E_ARG;
+  if (!m_dev) return fail(c, ORAS_E_ARG, "null m");
+  if (!c->assembled) return fail(c, ORAS_E_STATE, "set_m before assemble");
+  TRY(check_device(c));
+  const Table& t = weight_table();
+  c->release_factors();
+  launch_fields(nullptr, nullptr, m_dev, c->wtab.as<double>(), t.count, t.g0, t.dg, c->nx, c->ny,
+                c->nz, c->h, c->omega, c->w7.as<double>(), c->qf.as<double2>(), c->mt.as<double2>(),
+                c->stream, 1);
+  HIP_TRY(c, hipGetLastError());
+  TRY(build_coefficients(c));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return ORAS_OK;
+}
+
+oras_status oras_factor_subdomains(oras_ctx c, const int parts[3], int overlap, int factor_prec) {
+  if (!c) return ORAS_E_ARG;
+  if (!parts) return fail(c, ORAS_E_ARG, "null parts");
+  if (factor_prec != ORAS_C64 && factor_prec != ORAS_C128)
+    return fail(c, ORAS_E_ARG, "factor_prec must be ORAS_C64 or ORAS_C128");
+  if (overlap < 0 || overlap > 8) return fail(c, ORAS_E_ARG, "overlap must be 0..8");
+  for (int a = 0; a < 3; ++a)
+    if (parts[a] < 1 || parts[a] > 256) return fail(c, ORAS_E_ARG, "parts must be 1..256");
+  if (!c->assembled) return fail(c, ORAS_E_STATE, "factor_subdomains before assemble");
+  const int nn[3] = {c->nx, c->ny, c->nz};
+  for (int a = 0; a < 3; ++a)
+    if (parts[a] > nn[a] / 2) return fail(c, ORAS_E_ARG, "partition finer than 2 nodes per part");
+
+  // partition: floor split, overlap layers on interior sides (clipped)
+  std::vector<SubDesc> subs;
+  std::vector<int> cuts[3];
+  for (int a = 0; a < 3; ++a)
+    for (int t = 0; t <= parts[a]; ++t) cuts[a].push_back((int)(((long long)t * nn[a]) / parts[a]));
+  long long fac_off = 0, lca_off = 0, y_rows = 0, t_off = 0, tv_rows = 0;
+  int max_sz = 0, max_nt = 0;
+  long long max_p = 0, max_box = 0;
+  for (int tz = 0; tz < parts[2]; ++tz)
+    for (int ty = 0; ty < parts[1]; ++ty)
+      for (int tx = 0; tx < parts[0]; ++tx) {
+        SubDesc d;
+        std::memset(&d, 0, sizeof(d));
+        const int tt[3] = {tx, ty, tz};
+        for (int a = 0; a < 3; ++a) {
+          d.olo[a] = cuts[a][tt[a]];
+          d.ohi[a] = cuts[a][tt[a] + 1];
+          d.lo[a] = std::max(0, d.olo[a] - overlap);
+          d.hi[a] = std::min(nn[a], d.ohi[a] + overlap);
+        }
+        d.sx = d.hi[0] - d.lo[0];
+        d.sy = d.hi[1] - d.lo[1];
+        d.sz = d.hi[2] - d.lo[2];
+        if (d.sx < 2 || d.sy < 2 || d.sz < 2)
+          return fail(c, ORAS_E_ARG, "subdomain box thinner than 2 nodes");
+        d.p = d.sx * d.sy;
+        d.P = (d.p + TILE - 1) / TILE * TILE;
+        d.nt = d.P / TILE;
+        if (d.P > 8192) return fail(c, ORAS_E_ARG, "subdomain plane larger than 8192 nodes");
+        d.fac_off = fac_off;
+        d.lca_off = lca_off;
+        d.y_off = y_rows;
+        d.t_off = t_off;
+        d.tv_off = tv_rows;
+        fac_off += (long long)d.sz * d.P * d.P;
+        lca_off += 27LL * d.sx * d.sy * d.sz;
+        y_rows += (long long)d.sz * d.P;
+        t_off += (long long)d.P * d.P;
+        tv_rows += d.P;
+        max_sz = std::max(max_sz, d.sz);
+        max_nt = std::max(max_nt, d.nt);
+        max_p = std::max(max_p, (long long)d.P);
+        max_box = std::max(max_box, (long long)d.sx * d.sy * d.sz);
+        subs.push_back(d);
+      }
+  const size_t cs = csize(factor_prec);
+  const double need = (double)(fac_off + t_off + lca_off) * cs;
+  TRY(check_device(c));
+  c->release_factors();
+  TRY(check_free(c, need));
+  DevBuf tbuf;
+  TRY(dev_alloc(c, c->fac, (size_t)fac_off * cs));
+  oras_status st = dev_alloc(c, tbuf, (size_t)t_off * cs);
+  if (st != ORAS_OK) { c->release_factors(); return st; }
+  TRY(dev_alloc(c, c->lca, (size_t)lca_off * cs));
+  TRY(dev_alloc(c, c->subs_dev, subs.size() * sizeof(SubDesc)));
+  TRY(dev_alloc(c, c->owner, (size_t)(nn[0] + nn[1] + nn[2]) * sizeof(int)));
+  TRY(dev_alloc(c, c->status, subs.size() * sizeof(int)));
+  std::vector<int> own;
+  for (int a = 0; a < 3; ++a)
+    for (int i = 0; i < nn[a]; ++i) {
+      int t = 0;
+      while (!(cuts[a][t] <= i && i < cuts[a][t + 1])) ++t;
+      own.push_back(t);
+    }
+  HIP_TRY(c, hipMemcpyAsync(c->subs_dev.p, subs.data(), subs.size() * sizeof(SubDesc),
+                            hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->owner.p, own.data(), own.size() * sizeof(int), hipMemcpyHostToDevice,
+                            c->stream));
+  launch_zero(c->status.p, subs.size() * sizeof(int), c->stream);
+  const double t0 = now();
+  launch_assemble_local(opview(c), c->subs_dev.as<SubDesc>(), (int)subs.size(), max_box, c->lca.p,
+                        factor_prec, c->stream);
+  HIP_TRY(c, hipGetLastError());
+  for (int k = 0; k < max_sz; ++k) {
+    if (factor_prec == ORAS_C64)
+      launch_factor_plane<float>(c->subs_dev.as<SubDesc>(), (int)subs.size(), k, max_nt,
+                                 c->fac.as<float2>(), tbuf.as<float2>(), c->lca.as<float2>(),
+                                 c->status.as<int>(), c->stream);
+    else
+      launch_factor_plane<double>(c->subs_dev.as<SubDesc>(), (int)subs.size(), k, max_nt,
+                                  c->fac.as<double2>(), tbuf.as<double2>(), c->lca.as<double2>(),
+                                  c->status.as<int>(), c->stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+      tbuf.release();
+      c->release_factors();
+      return fail(c, ORAS_E_HIP, std::string("factor launch: ") + hipGetErrorString(e));
+    }
+  }
+  std::vector<int> stat(subs.size(), 0);
+  HIP_TRY(c, hipMemcpyAsync(stat.data(), c->status.p, stat.size() * sizeof(int),
+                            hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  tbuf.release();
+  c->t_factor = now() - t0;
+  for (size_t j = 0; j < stat.size(); ++j)
+    if (stat[j]) {
+      c->release_factors();
+      return fail(c, ORAS_E_NUMERIC,
+                  "zero or non-finite pivot while factoring subdomain " + std::to_string(j));
+    }
+  c->subs = subs;
+  c->factor_prec = factor_prec;
+  c->parts[0] = parts[0];
+  c->parts[1] = parts[1];
+  c->parts[2] = parts[2];
+  c->overlap = overlap;
+  c->max_sz = max_sz;
+  c->max_nt = max_nt;
+  c->max_p = max_p;
+  c->max_box = max_box;
+  c->y_rows = y_rows;
+  c->tv_rows = tv_rows;
+  c->factored = true;
+  return ORAS_OK;
+}
+
+oras_status oras_subdomain(oras_ctx c, int j, int* nsub, int* box12) {
+  if (!c) return ORAS_E_ARG;
+  if (!c->factored) return fail(c, ORAS_E_STATE, "no factors");
+  if (nsub) *nsub = (int)c->subs.size();
+  if (!box12) return ORAS_OK;
+  if (j < 0 || j >= (int)c->subs.size()) return fail(c, ORAS_E_ARG, "subdomain index out of range");
+  const SubDesc& d = c->subs[j];
+  for (int a = 0; a < 3; ++a) {
+    box12[a] = d.lo[a];
+    box12[3 + a] = d.hi[a];
+    box12[6 + a] = d.olo[a];
+    box12[9 + a] = d.ohi[a];
+  }
+  return ORAS_OK;
+}
+
+oras_status oras_apply_A(oras_ctx c, const void* x_dev, void* y_dev, int nrhs, int prec) {
+  if (!c) return ORAS_E_ARG;
+  if (!x_dev || !y_dev) return fail(c, ORAS_E_ARG, "null vector");
+  if (nrhs < 1 || nrhs > 256) return fail(c, ORAS_E_ARG, "nrhs must be 1..256");
+  if (prec != ORAS_C64 && prec != ORAS_C128) return fail(c, ORAS_E_ARG, "bad precision");
+  if (!c->assembled) return fail(c, ORAS_E_STATE, "apply_A before assemble");
+  if (prec == ORAS_C64 && c->stencil_prec != ORAS_C64)
+    return fail(c, ORAS_E_STATE, "no complex64 stencil assembled");
+  TRY(check_device(c));
+  const long long s = pad_s(nrhs);
+  TRY(dev_alloc(c, c->Bint, (size_t)(c->n * s) * sizeof(double2)));
+  TRY(dev_alloc(c, c->Tmp, (size_t)(c->n * s) * sizeof(double2)));
+  launch_to_internal((const double2*)x_dev, c->Bint.as<double2>(), c->n, nrhs, (int)s, 0, c->stream);
+  TRY(stencil_internal(c, c->Bint.as<double2>(), nullptr, c->Tmp.as<double2>(), (int)s, prec));
+  launch_from_internal(c->Tmp.as<double2>(), (double2*)y_dev, c->n, nrhs, (int)s, 0, c->stream);
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return ORAS_OK;
+}
+
+oras_status oras_apply_M(oras_ctx c, const void* x_dev, void* y_dev, int nrhs) {
+  if (!c) return ORAS_E_ARG;
+  if (!x_dev || !y_dev) return fail(c, ORAS_E_ARG, "null vector");
+  if (nrhs < 1 || nrhs > 256) return fail(c, ORAS_E_ARG, "nrhs must be 1..256");
+  if (!c->factored) return fail(c, ORAS_E_STATE, "apply_M before factor_subdomains");
+  TRY(check_device(c));
+  const long long s = pad_s(nrhs);
+  TRY(dev_alloc(c, c->Bint, (size_t)(c->n * s) * sizeof(double2)));
+  TRY(dev_alloc(c, c->Tmp, (size_t)(c->n * s) * sizeof(double2)));
+  launch_to_internal((const double2*)x_dev, c->Bint.as<double2>(), c->n, nrhs, (int)s, 0, c->stream);
+  TRY(oras_apply_internal(c, c->Bint.as<double2>(), nullptr, c->Tmp.p, (int)s, true));
+  launch_from_internal(c->Tmp.as<double2>(), (double2*)y_dev, c->n, nrhs, (int)s, 0, c->stream);
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return ORAS_OK;
+}
+
+oras_status oras_coefficients(oras_ctx c, void* out_dev) {
+  if (!c) return ORAS_E_ARG;
+  if (!out_dev) return fail(c, ORAS_E_ARG, "null output");
+  if (!c->assembled) return fail(c, ORAS_E_STATE, "coefficients before assemble");
+  TRY(check_device(c));
+  HIP_TRY(c, hipMemcpyAsync(out_dev, c->coef128.p, (size_t)c->n * 27 * sizeof(double2),
+                            hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return ORAS_OK;
+}
+
+oras_status oras_solve(oras_ctx c, const void* b_dev, void* x_dev, int nrhs, double tol,
+                       const oras_solve_opts* opts, oras_solve_info* info) {
+  if (!c) return ORAS_E_ARG;
+  if (!b_dev || !x_dev) return fail(c, ORAS_E_ARG, "null b or x");
+  if (nrhs < 1 || nrhs > 256) return fail(c, ORAS_E_ARG, "nrhs must be 1..256");
+  if (!(tol > 0.0 && tol < 1.0)) return fail(c, ORAS_E_ARG, "tol must be in (0, 1)");
+  oras_solve_opts o = {30, 1000, 0, 0};
+  if (opts) o = *opts;
+  if (o.restart < 1 || o.restart > 200) return fail(c, ORAS_E_ARG, "restart must be 1..200");
+  if (o.maxit < 1) return fail(c, ORAS_E_ARG, "maxit must be >= 1");
+  if (o.flags & ~(ORAS_CONJ | ORAS_X0)) return fail(c, ORAS_E_ARG, "unknown flags");
+  if (!c->assembled) return fail(c, ORAS_E_STATE, "solve before assemble");
+  if (!c->factored) return fail(c, ORAS_E_STATE, "solve before factor_subdomains");
+  if (c->stencil_prec != c->factor_prec)
+    return fail(c, ORAS_E_ARG, "stencil and factor precisions must match");
+  TRY(check_device(c));
+  const double t0 = now();
+  const hipStream_t st = c->stream;
+  const int m = o.restart;
+  const long long s = pad_s(nrhs);
+  const long long n = c->n;
+  const long long ns = n * s;
+  const bool mixed = (c->factor_prec == ORAS_C64);
+  const size_t zsz = mixed ? sizeof(float2) : sizeof(double2);
+  const int nblk = nblk_for(n);
+  {
+    double need = 0;
+    if (!c->V.p || c->ws_s < s || c->ws_m < m) need += (double)ns * ((m + 1) * 16.0 + m * zsz + 2 * 16.0);
+    TRY(check_free(c, need));
+  }
+  if (c->ws_s < s || c->ws_m < m) c->release_workspace();
+  TRY(dev_alloc(c, c->V, (size_t)((m + 1) * ns) * sizeof(double2)));
+  TRY(dev_alloc(c, c->Z, (size_t)(m * ns) * zsz));
+  TRY(dev_alloc(c, c->Bint, (size_t)ns * sizeof(double2)));
+  TRY(dev_alloc(c, c->Xint, (size_t)ns * sizeof(double2)));
+  TRY(dev_alloc(c, c->partial, (size_t)nblk * (m + 1) * s * sizeof(double2)));
+  // small per-column state
+  const size_t sH = (size_t)(m + 1) * m * s, sG = (size_t)(m + 1) * s;
+  const size_t small_bytes = sizeof(double2) * (sH + sG * 4 + (size_t)m * s) + sizeof(double) * (sG + (size_t)m * s + 8 * s) +
+                             sizeof(int) * 8 * s + 4096;
+  TRY(dev_alloc(c, c->small, small_bytes));
+  c->ws_s = std::max(c->ws_s, s);
+  c->ws_m = std::max(c->ws_m, m);
+  TRY(ensure_oras_ws(c, s));
+  char* sp = c->small.as<char>();
+  auto carve = [&](size_t bytes) { char* p = sp; sp += (bytes + 255) / 256 * 256; return (void*)p; };
+  double2* H = (double2*)carve(sizeof(double2) * sH);
+  double2* g = (double2*)carve(sizeof(double2) * sG);
+  double2* hv = (double2*)carve(sizeof(double2) * sG);
+  double2* hs = (double2*)carve(sizeof(double2) * sG);
+  double2* y = (double2*)carve(sizeof(double2) * sG);
+  double2* sn = (double2*)carve(sizeof(double2) * (size_t)m * s);
+  double* scale = (double*)carve(sizeof(double) * sG);
+  double* cs = (double*)carve(sizeof(double) * (size_t)m * s);
+  double* bnorm = (double*)carve(sizeof(double) * s);
+  double* beta = (double*)carve(sizeof(double) * s);
+  double* est = (double*)carve(sizeof(double) * s);
+  int* jc = (int*)carve(sizeof(int) * s);
+  int* done = (int*)carve(sizeof(int) * s);
+  int* conv_d = (int*)carve(sizeof(int) * s);
+  double* npart = (double*)c->partial.p;
+  double2* dpart = (double2*)c->partial.p;
+
+  double2* V = c->V.as<double2>();
+  double2* B = c->Bint.as<double2>();
+  double2* X = c->Xint.as<double2>();
+  const int conj = (o.flags & ORAS_CONJ) ? 1 : 0;
+  launch_to_internal((const double2*)b_dev, B, n, nrhs, (int)s, conj, st);
+  if (o.flags & ORAS_X0) launch_to_internal((const double2*)x_dev, X, n, nrhs, (int)s, conj, st);
+  else launch_zero(X, (size_t)ns * sizeof(double2), st);
+  launch_colnorm2(B, n, (int)s, npart, nblk, st);
+  launch_finish_norm(npart, nblk, (int)s, bnorm, st);
+  std::vector<double> h_bnorm(s), h_beta(s);
+  std::vector<int> h_conv(s, 0), h_done(s, 0), h_iters(s, 0);
+  HIP_TRY(c, hipMemcpyAsync(h_bnorm.data(), bnorm, s * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(c, hipGetLastError());
+
+  hipEvent_t ev[4];
+  for (int i = 0; i < 4; ++i) HIP_TRY(c, hipEventCreate(&ev[i]));
+  double t_sten = 0, t_oras = 0, t_orth = 0;
+  int cycles = 0, total = 0;
+  oras_status result = ORAS_OK;
+
+  auto true_residual = [&]() -> oras_status {
+    TRY(stencil_internal(c, X, B, V, (int)s, ORAS_C128));
+    launch_colnorm2(V, n, (int)s, npart, nblk, st);
+    launch_finish_norm(npart, nblk, (int)s, beta, st);
+    HIP_TRY(c, hipMemcpyAsync(h_beta.data(), beta, s * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+    for (long long col = 0; col < s; ++col) {
+      if (!std::isfinite(h_beta[col])) return fail(c, ORAS_E_NUMERIC, "non-finite residual");
+      h_conv[col] = (h_bnorm[col] == 0.0) || (h_beta[col] <= tol * h_bnorm[col]);
+    }
+    return ORAS_OK;
+  };
+
+  oras_status rs = true_residual();
+  if (rs != ORAS_OK) result = rs;
+  while (result == ORAS_OK) {
+    bool any = false;
+    for (long long col = 0; col < s; ++col) any |= !h_conv[col];
+    if (!any || total >= o.maxit) break;
+    HIP_TRY(c, hipMemcpyAsync(conv_d, h_conv.data(), s * sizeof(int), hipMemcpyHostToDevice, st));
+    launch_cycle_init((int)s, m, beta, conv_d, g, scale, jc, done, st);
+    for (long long col = 0; col < s; ++col) h_done[col] = h_conv[col];
+    int j = 0;
+    for (; j < m; ++j) {
+      void* Zj = c->Z.as<char>() + (size_t)j * ns * zsz;
+      double2* Vj = V + (size_t)j * ns;
+      double2* Vn = V + (size_t)(j + 1) * ns;
+      HIP_TRY(c, hipEventRecord(ev[0], st));
+      TRY(oras_apply_internal(c, Vj, scale + j * s, Zj, (int)s, !mixed));
+      HIP_TRY(c, hipEventRecord(ev[1], st));
+      if (mixed)
+        launch_stencil<float>(c->coef64.as<float2>(), (const float2*)Zj, nullptr, Vn, c->nx, c->ny,
+                              c->nz, (int)s, st);
+      else
+        launch_stencil<double>(c->coef128.as<double2>(), (const double2*)Zj, nullptr, Vn, c->nx,
+                               c->ny, c->nz, (int)s, st);
+      HIP_TRY(c, hipEventRecord(ev[2], st));
+      launch_cgs_dot(V, ns, j + 1, Vn, n, (int)s, dpart, nblk, st);
+      launch_cgs_finish_dot(dpart, nblk, j + 1, (int)s, scale, hv, hs, st);
+      launch_cgs_update(V, ns, j + 1, hs, Vn, n, (int)s, npart, nblk, st);
+      launch_arnoldi_step(j, m, (int)s, npart, nblk, hv, H, cs, sn, g, scale + (j + 1) * s, jc,
+                          done, bnorm, tol, est, st);
+      HIP_TRY(c, hipEventRecord(ev[3], st));
+      HIP_TRY(c, hipGetLastError());
+      for (long long col = 0; col < s; ++col)
+        if (!h_done[col]) h_iters[col] += 1;
+      HIP_TRY(c, hipMemcpyAsync(h_done.data(), done, s * sizeof(int), hipMemcpyDeviceToHost, st));
+      HIP_TRY(c, hipStreamSynchronize(st));
+      float ms = 0;
+      HIP_TRY(c, hipEventElapsedTime(&ms, ev[0], ev[1])); t_oras += ms * 1e-3;
+      HIP_TRY(c, hipEventElapsedTime(&ms, ev[1], ev[2])); t_sten += ms * 1e-3;
+      HIP_TRY(c, hipEventElapsedTime(&ms, ev[2], ev[3])); t_orth += ms * 1e-3;
+      ++total;
+      bool all = true, bad = false;
+      for (long long col = 0; col < s; ++col) {
+        all &= (h_done[col] != 0);
+        bad |= (h_done[col] == 2);
+      }
+      if (bad) { result = fail(c, ORAS_E_NUMERIC, "non-finite value in the Arnoldi process"); break; }
+      if (all || total >= o.maxit) { ++j; break; }
+    }
+    if (result != ORAS_OK) break;
+    launch_backsolve(m, (int)s, H, g, jc, y, st);
+    if (mixed)
+      launch_update_x<float2>(c->Z.as<float2>(), ns, y, jc, X, n, (int)s, st);
+    else
+      launch_update_x<double2>(c->Z.as<double2>(), ns, y, jc, X, n, (int)s, st);
+    HIP_TRY(c, hipGetLastError());
+    ++cycles;
+    rs = true_residual();
+    if (rs != ORAS_OK) { result = rs; break; }
+  }
+  for (int i = 0; i < 4; ++i) (void)hipEventDestroy(ev[i]);
+  if (result != ORAS_OK) return result;
+  // columns with b = 0 return exactly 0
+  for (long long col = 0; col < nrhs; ++col)
+    if (h_bnorm[col] == 0.0) launch_zero_column(X, n, (int)s, (int)col, st);
+  launch_from_internal(X, (double2*)x_dev, n, nrhs, (int)s, conj, st);
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipStreamSynchronize(st));
+  bool allconv = true;
+  for (int col = 0; col < nrhs; ++col) allconv &= (h_conv[col] != 0);
+  if (info) {
+    for (int col = 0; col < nrhs; ++col) {
+      if (info->iters) info->iters[col] = h_iters[col];
+      if (info->rel_res) info->rel_res[col] = h_bnorm[col] > 0 ? h_beta[col] / h_bnorm[col] : 0.0;
+      if (info->converged) info->converged[col] = h_conv[col];
+    }
+    info->t_solve = now() - t0;
+    info->t_stencil = t_sten;
+    info->t_oras = t_oras;
+    info->t_ortho = t_orth;
+    info->cycles = cycles;
+    info->total_iters = total;
+  }
+  if (!allconv) {
+    c->err = "some columns did not reach tol within maxit";
+    return ORAS_W_NOT_CONVERGED;
+  }
+  return ORAS_OK;
+}
+
+oras_status oras_point_sources(oras_ctx c, const int* idx_host, const double* amp_host, int nrhs,
+                               void* b_dev) {
+  if (!c) return ORAS_E_ARG;
+  if (!idx_host || !b_dev) return fail(c, ORAS_E_ARG, "null indices or output");
+  if (nrhs < 1 || nrhs > 4096) return fail(c, ORAS_E_ARG, "nrhs must be 1..4096");
+  if (!c->assembled) return fail(c, ORAS_E_STATE, "point_sources before assemble");
+  for (int q = 0; q < nrhs; ++q) {
+    const int i = idx_host[3 * q], j = idx_host[3 * q + 1], k = idx_host[3 * q + 2];
+    if (i < 0 || i >= c->nx || j < 0 || j >= c->ny || k < 0 || k >= c->nz)
+      return fail(c, ORAS_E_ARG, "source index outside the grid");
+  }
+  TRY(check_device(c));
+  DevBuf idx, amp;
+  TRY(dev_alloc(c, idx, sizeof(int) * 3 * nrhs));
+  if (amp_host) TRY(dev_alloc(c, amp, sizeof(double) * 2 * nrhs));
+  HIP_TRY(c, hipMemcpyAsync(idx.p, idx_host, sizeof(int) * 3 * nrhs, hipMemcpyHostToDevice, c->stream));
+  if (amp_host)
+    HIP_TRY(c, hipMemcpyAsync(amp.p, amp_host, sizeof(double) * 2 * nrhs, hipMemcpyHostToDevice,
+                              c->stream));
+  launch_zero(b_dev, (size_t)c->n * nrhs * sizeof(double2), c->stream);
+  launch_point_sources(idx.as<int>(), amp_host ? amp.as<double>() : nullptr, nrhs,
+                       c->px.as<double2>(), c->py.as<double2>(), c->pz.as<double2>(), c->nx, c->ny,
+                       c->nz, (double2*)b_dev, c->stream);
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  idx.release();
+  amp.release();
+  return ORAS_OK;
+}
+
+oras_status oras_sample(oras_ctx c, const void* u_dev, int nrhs, const int* rec_dev, int nrec,
+                        void* d_dev) {
+  if (!c) return ORAS_E_ARG;
+  if (!u_dev || !rec_dev || !d_dev) return fail(c, ORAS_E_ARG, "null pointer");
+  if (nrhs < 1 || nrec < 1) return fail(c, ORAS_E_ARG, "nrhs and nrec must be >= 1");
+  if (!c->assembled) return fail(c, ORAS_E_STATE, "sample before assemble");
+  TRY(check_device(c));
+  TRY(check_receivers(c, rec_dev, nrec));
+  launch_sample((const double2*)u_dev, c->n, nrhs, rec_dev, nrec, c->nx, c->ny, (double2*)d_dev,
+                c->stream);
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return ORAS_OK;
+}
+
+oras_status oras_spread(oras_ctx c, const void* d_dev, int nrhs, const int* rec_dev, int nrec,
+                        void* b_dev) {
+  if (!c) return ORAS_E_ARG;
+  if (!d_dev || !rec_dev || !b_dev) return fail(c, ORAS_E_ARG, "null pointer");
+  if (nrhs < 1 || nrec < 1) return fail(c, ORAS_E_ARG, "nrhs and nrec must be >= 1");
+  if (!c->assembled) return fail(c, ORAS_E_STATE, "spread before assemble");
+  TRY(check_device(c));
+  TRY(check_receivers(c, rec_dev, nrec));
+  launch_zero(b_dev, (size_t)c->n * nrhs * sizeof(double2), c->stream);
+  launch_spread((const double2*)d_dev, c->n, nrhs, rec_dev, nrec, c->nx, c->ny, (double2*)b_dev,
+                c->stream);
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return ORAS_OK;
+}
+
+oras_status oras_gradient(oras_ctx c, const void* u_dev, const void* mu_dev, int nrhs,
+                          double* g_dev) {
+  if (!c) return ORAS_E_ARG;
+  if (!u_dev || !mu_dev || !g_dev) return fail(c, ORAS_E_ARG, "null pointer");
+  if (nrhs < 1) return fail(c, ORAS_E_ARG, "nrhs must be >= 1");
+  if (!c->assembled) return fail(c, ORAS_E_STATE, "gradient before assemble");
+  TRY(check_device(c));
+  launch_gradient(opview(c), c->qf.as<double2>(), (const double2*)u_dev, (const double2*)mu_dev,
+                  nrhs, g_dev, c->stream);
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return ORAS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,150 @@
+// Internal declarations of the ORAS-FGMRES Helmholtz library (gfx950).
+// Shared by the host driver and the kernel translation units only.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/oras.h"
+
+namespace oras {
+
+// ---------------------------------------------------------------- complex --
+template <typename R> struct cplx;
+template <> struct cplx<float> { using type = float2; };
+template <> struct cplx<double> { using type = double2; };
+template <typename R> using C = typename cplx<R>::type;
+
+template <typename R> __host__ __device__ inline C<R> mk(R a, R b) { C<R> z; z.x = a; z.y = b; return z; }
+template <typename T> __host__ __device__ inline T cadd(T a, T b) { a.x += b.x; a.y += b.y; return a; }
+template <typename T> __host__ __device__ inline T csub(T a, T b) { a.x -= b.x; a.y -= b.y; return a; }
+template <typename T> __host__ __device__ inline T cmul(T a, T b) {
+  T z; z.x = a.x * b.x - a.y * b.y; z.y = a.x * b.y + a.y * b.x; return z;
+}
+// acc += a * b
+template <typename T> __host__ __device__ inline void cfma(T& acc, T a, T b) {
+  acc.x += a.x * b.x - a.y * b.y; acc.y += a.x * b.y + a.y * b.x;
+}
+// acc += conj(a) * b
+template <typename T> __host__ __device__ inline void cfmaconj(T& acc, T a, T b) {
+  acc.x += a.x * b.x + a.y * b.y; acc.y += a.x * b.y - a.y * b.x;
+}
+template <typename T> __host__ __device__ inline T cscale(T a, double s) { a.x *= s; a.y *= s; return a; }
+__host__ __device__ inline double2 cdiv(double2 a, double2 b) {
+  double d = b.x * b.x + b.y * b.y;
+  return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+__host__ __device__ inline double2 cinv(double2 b) {
+  double d = b.x * b.x + b.y * b.y;
+  return make_double2(b.x / d, -b.y / d);
+}
+template <typename To, typename From> __host__ __device__ inline To ccast(From a) {
+  To z; z.x = a.x; z.y = a.y; return z;
+}
+
+// ---------------------------------------------------------------- layouts --
+constexpr int TILE = 32;        // factor tile edge (complex entries)
+constexpr int RHS_ALIGN = 8;    // internal right-hand-side count granularity
+
+// Neighbour offset (ex, ey, ez) in {-1,0,1}^3 -> coefficient slot.
+__host__ __device__ constexpr inline int eidx(int ex, int ey, int ez) {
+  return (ez + 1) * 9 + (ey + 1) * 3 + (ex + 1);
+}
+
+// Operator description visible to the assembly kernels (all device memory).
+struct OpView {
+  int nx, ny, nz;
+  double h, omega;
+  const double* w7;      // (n, 7): w1 w2 w3 wm0 wmf wme wmc per node
+  const double2* mt;     // (n) complex squared slowness
+  const double2* px;     // PML profile on the half grid, length 2 nx + 1
+  const double2* py;
+  const double2* pz;
+};
+
+// One overlapping subdomain: box [lo, hi) and owned cuboid [olo, ohi).
+struct SubDesc {
+  int lo[3], hi[3], olo[3], ohi[3];
+  int sx, sy, sz;        // box extents
+  int p;                 // plane size sx*sy
+  int P;                 // padded plane size (multiple of TILE)
+  int nt;                // P / TILE
+  int pad_;
+  long long fac_off;     // complex offset of plane 0's inverse in the factor buffer
+  long long lca_off;     // offset of the local coefficient array (27 * sx*sy*sz)
+  long long y_off;       // offset of the local solution buffer (sz * P * s)  [in units of P*s]
+  long long t_off;       // offset of the scratch plane (P*P) used while factoring
+  long long tv_off;      // offset of the plane right-hand side (P * s)
+};
+
+// ------------------------------------------------------------- launchers --
+// Assembly
+void launch_assemble_global(const OpView& op, double2* coef128, float2* coef64, hipStream_t s);
+void launch_assemble_local(const OpView& op, const SubDesc* subs_dev, int nsub, long long max_box,
+                           void* lca, int prec, hipStream_t s);
+void launch_fields(const double* vel, const double* q, const double* m_override, const double* wtab,
+                   int tab_count, double g0, double dg, int nx, int ny, int nz, double h,
+                   double omega, double* w7, double2* qfac, double2* mt, hipStream_t s,
+                   int keep_weights);
+void launch_pml(double2* prof, int n, int npml, double h, double omega, double c_ref, double R0,
+                int power, int low, int high, hipStream_t s);
+void launch_max_reduce(const double* x, long long n, double* out, hipStream_t s);
+
+// Stencil: y = A x (or y = b - A x when b != null).  x precision Tx, coefficient
+// precision Tc (== Tx), output double2.
+template <typename R>
+void launch_stencil(const C<R>* coef, const C<R>* x, const double2* b, double2* y, int nx, int ny,
+                    int nz, int s, hipStream_t st);
+
+// Factorisation, one plane for all subdomains
+template <typename R>
+void launch_factor_plane(const SubDesc* subs_dev, int nsub, int k, int max_nt, C<R>* fac,
+                         C<R>* tbuf, const C<R>* lca, int* status, hipStream_t st);
+
+// Tri-solve (ORAS apply).  Input v (double2, global [n][s]) times per-column scale
+// (may be null) -> output z (global [n][s], precision Z).
+template <typename R, typename Z>
+void launch_oras_apply(const SubDesc* subs_dev, int nsub, int max_sz, int max_nt, long long max_p,
+                       const C<R>* fac, const C<R>* lca, C<R>* ybuf, C<R>* tvbuf,
+                       const double2* v, const double* scale, Z* z, int nx, int ny, int nz,
+                       int s, const int* owner_dev, int parts_x, int parts_y, hipStream_t st);
+
+// Krylov helpers
+void launch_to_internal(const double2* src, double2* dst, long long n, int nrhs, int s, int conj,
+                        hipStream_t st);
+void launch_from_internal(const double2* src, double2* dst, long long n, int nrhs, int s, int conj,
+                          hipStream_t st);
+void launch_colnorm2(const double2* x, long long n, int s, double* partial, int nblk, hipStream_t st);
+void launch_finish_norm(const double* partial, int nblk, int s, double* out, hipStream_t st);
+void launch_cgs_dot(const double2* V, long long vstride, int j1, const double2* w, long long n,
+                    int s, double2* partial, int nblk, hipStream_t st);
+void launch_cgs_finish_dot(const double2* partial, int nblk, int j1, int s, const double* scale,
+                           double2* h, double2* hs, hipStream_t st);
+void launch_cgs_update(const double2* V, long long vstride, int j1, const double2* hs, double2* w,
+                       long long n, int s, double* partial, int nblk, hipStream_t st);
+void launch_arnoldi_step(int j, int m, int s, const double* norm_partial, int nblk,
+                         const double2* h, double2* H, double* cs, double2* sn, double2* g,
+                         double* scale_next, int* jc, int* done, const double* bnorm, double tol,
+                         double* est, hipStream_t st);
+void launch_cycle_init(int s, int m, const double* beta, const int* conv, double2* g,
+                       double* scale0, int* jc, int* done, hipStream_t st);
+void launch_backsolve(int m, int s, const double2* H, const double2* g, const int* jc, double2* y,
+                      hipStream_t st);
+template <typename Z>
+void launch_update_x(const Z* Zb, long long zstride, const double2* y, const int* jc, double2* x,
+                     long long n, int s, hipStream_t st);
+void launch_zero(void* p, size_t bytes, hipStream_t st);
+void launch_zero_column(double2* x, long long n, int s, int col, hipStream_t st);
+void launch_point_sources(const int* idx, const double* amp, int nrhs, const double2* px,
+                          const double2* py, const double2* pz, int nx, int ny, int nz,
+                          double2* b, hipStream_t st);
+void launch_sample(const double2* u, long long n, int nrhs, const int* rec, int nrec, int nx,
+                   int ny, double2* d, hipStream_t st);
+void launch_spread(const double2* d, long long n, int nrhs, const int* rec, int nrec, int nx,
+                   int ny, double2* b, hipStream_t st);
+void launch_gradient(const OpView& op, const double2* qfac, const double2* u, const double2* mu,
+                     int nrhs, double* g, hipStream_t st);
+template <typename R>
+void launch_cast(const double2* src, C<R>* dst, long long count, hipStream_t st);
+
+}  // namespace oras

@@ -1,0 +1,307 @@
+"""Thin ctypes binding of liboras.so (argument marshalling only).
+
+Every step of the solver runs in the HIP library; this module only checks
+tensor placement, dtype and contiguity, passes device pointers and the
+current HIP stream, and raises on error codes.  The library is loaded from
+this package folder; when it is missing the import fails loudly (there is no
+CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboras.so")
+
+C64 = 1
+C128 = 2
+CONJ = 1
+X0 = 2
+
+STATUS = {0: "ORAS_OK", 1: "ORAS_E_ARG", 2: "ORAS_E_STATE", 3: "ORAS_E_OOM", 4: "ORAS_E_HIP",
+          5: "ORAS_E_NUMERIC", 100: "ORAS_W_NOT_CONVERGED"}
+
+
+class OrasError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Grid(ct.Structure):
+    _fields_ = [("nx", ct.c_int), ("ny", ct.c_int), ("nz", ct.c_int), ("h", ct.c_double),
+                ("npml", ct.c_int), ("free_surface", ct.c_int)]
+
+
+class Pml(ct.Structure):
+    _fields_ = [("R0", ct.c_double), ("power", ct.c_int), ("c_ref", ct.c_double)]
+
+
+class SolveOpts(ct.Structure):
+    _fields_ = [("restart", ct.c_int), ("maxit", ct.c_int), ("flags", ct.c_int),
+                ("reserved", ct.c_int)]
+
+
+class SolveInfo(ct.Structure):
+    _fields_ = [("iters", ct.POINTER(ct.c_int)), ("rel_res", ct.POINTER(ct.c_double)),
+                ("converged", ct.POINTER(ct.c_int)), ("t_solve", ct.c_double),
+                ("t_stencil", ct.c_double), ("t_oras", ct.c_double), ("t_ortho", ct.c_double),
+                ("cycles", ct.c_int), ("total_iters", ct.c_int)]
+
+
+_LIB = None
+
+SIGNATURES = {
+    "oras_create": (ct.c_int, [ct.POINTER(ct.c_void_p), ct.c_int, ct.c_void_p]),
+    "oras_destroy": (None, [ct.c_void_p]),
+    "oras_last_error": (ct.c_char_p, [ct.c_void_p]),
+    "oras_weight_table": (ct.c_int, [ct.c_void_p, ct.c_int, ct.POINTER(ct.c_double),
+                                     ct.POINTER(ct.c_double), ct.POINTER(ct.c_int)]),
+    "oras_assemble": (ct.c_int, [ct.c_void_p, ct.POINTER(Grid), ct.c_void_p, ct.c_void_p,
+                                 ct.c_double, ct.POINTER(Pml), ct.c_int]),
+    "oras_set_m": (ct.c_int, [ct.c_void_p, ct.c_void_p]),
+    "oras_factor_subdomains": (ct.c_int, [ct.c_void_p, ct.POINTER(ct.c_int), ct.c_int, ct.c_int]),
+    "oras_solve": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_double,
+                              ct.POINTER(SolveOpts), ct.POINTER(SolveInfo)]),
+    "oras_point_sources": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int,
+                                      ct.c_void_p]),
+    "oras_sample": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_int,
+                               ct.c_void_p]),
+    "oras_spread": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_int,
+                               ct.c_void_p]),
+    "oras_gradient": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_void_p]),
+    "oras_apply_A": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_int]),
+    "oras_apply_M": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int]),
+    "oras_timings": (ct.c_int, [ct.c_void_p, ct.POINTER(ct.c_double), ct.POINTER(ct.c_double)]),
+    "oras_coefficients": (ct.c_int, [ct.c_void_p, ct.c_void_p]),
+    "oras_subdomain": (ct.c_int, [ct.c_void_p, ct.c_int, ct.POINTER(ct.c_int),
+                                  ct.POINTER(ct.c_int)]),
+}
+
+
+def lib():
+    """Load liboras.so from the package folder (raises if it is not built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2110_15113_amd.build`")
+        L = ct.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def weight_table():
+    """The library's own fitted weight table: (G grid, (count, 7) weights)."""
+    L = lib()
+    cnt = ct.c_int()
+    g0 = ct.c_double()
+    dg = ct.c_double()
+    L.oras_weight_table(None, 0, ct.byref(g0), ct.byref(dg), ct.byref(cnt))
+    out = np.zeros((cnt.value, 7))
+    rc = L.oras_weight_table(out.ctypes.data_as(ct.c_void_p), cnt.value, None, None, None)
+    if rc != 0:
+        raise OrasError(rc, "weight table")
+    return g0.value + dg.value * np.arange(cnt.value), out
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ct.c_void_p(t.data_ptr())
+
+
+def _need(t: torch.Tensor, dtype, device, shape=None, name="tensor"):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.device != device:
+        raise ValueError(f"{name} must live on {device}, got {t.device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
+@dataclass
+class SolveResult:
+    x: torch.Tensor
+    iters: np.ndarray
+    rel_res: np.ndarray
+    converged: np.ndarray
+    t_solve: float
+    t_stencil: float
+    t_oras: float
+    t_ortho: float
+    cycles: int
+    total_iters: int
+    status: int
+
+
+class Solver:
+    """One library context: a grid, its operator, its subdomain factors."""
+
+    def __init__(self, device: int = 0, host_only: bool = False):
+        L = lib()
+        self._ctx = ct.c_void_p()
+        if host_only:
+            self.device = None
+            stream = None
+            dev = -1
+        else:
+            self.device = torch.device("cuda", device)
+            stream = ct.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+            dev = device
+        rc = L.oras_create(ct.byref(self._ctx), dev, stream)
+        if rc != 0:
+            raise OrasError(rc, f"oras_create(device={dev}) failed")
+        self.shape = None
+
+    def close(self):
+        if getattr(self, "_ctx", None) and self._ctx.value:
+            lib().oras_destroy(self._ctx)
+            self._ctx = ct.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int, allow_warn: bool = False):
+        if rc == 0 or (allow_warn and rc == 100):
+            return rc
+        raise OrasError(rc, lib().oras_last_error(self._ctx).decode())
+
+    # -- set-up ------------------------------------------------------------
+    def assemble(self, vel: torch.Tensor, h: float, npml: int, omega: float,
+                 Q: Optional[torch.Tensor] = None, prec: int = C128, R0: float = 1e-3,
+                 power: int = 2, c_ref: float = 0.0, free_surface: bool = False):
+        nz, ny, nx = vel.shape
+        _need(vel, torch.float64, self.device or vel.device, name="vel")
+        if Q is not None:
+            _need(Q, torch.float64, vel.device, vel.shape, name="Q")
+        g = Grid(nx, ny, nz, float(h), int(npml), int(bool(free_surface)))
+        p = Pml(float(R0), int(power), float(c_ref))
+        self._check(lib().oras_assemble(self._ctx, ct.byref(g), _ptr(vel), _ptr(Q), float(omega),
+                                        ct.byref(p), int(prec)))
+        self.shape = (nz, ny, nx)
+        self.prec = prec
+
+    def set_m(self, m: torch.Tensor):
+        _need(m, torch.float64, self.device, self.shape, name="m")
+        self._check(lib().oras_set_m(self._ctx, _ptr(m)))
+
+    def factor(self, parts: Sequence[int], overlap: int = 2, prec: int = C128):
+        arr = (ct.c_int * 3)(*[int(p) for p in parts])
+        self._check(lib().oras_factor_subdomains(self._ctx, arr, int(overlap), int(prec)))
+
+    def timings(self):
+        ta, tf = ct.c_double(), ct.c_double()
+        self._check(lib().oras_timings(self._ctx, ct.byref(ta), ct.byref(tf)))
+        return ta.value, tf.value
+
+    # -- solve -------------------------------------------------------------
+    def solve(self, b: torch.Tensor, tol: float, restart: int = 30, maxit: int = 1000,
+              conj: bool = False, x0: Optional[torch.Tensor] = None,
+              out: Optional[torch.Tensor] = None) -> SolveResult:
+        nrhs = b.shape[0]
+        _need(b, torch.complex128, self.device, (nrhs,) + self.shape, name="b")
+        flags = CONJ if conj else 0
+        if out is None:
+            out = torch.empty_like(b)
+        _need(out, torch.complex128, self.device, b.shape, name="out")
+        if x0 is not None:
+            _need(x0, torch.complex128, self.device, b.shape, name="x0")
+            out.copy_(x0)
+            flags |= X0
+        it = (ct.c_int * nrhs)()
+        rr = (ct.c_double * nrhs)()
+        cv = (ct.c_int * nrhs)()
+        info = SolveInfo(it, rr, cv, 0.0, 0.0, 0.0, 0.0, 0, 0)
+        opts = SolveOpts(int(restart), int(maxit), flags, 0)
+        rc = self._check(lib().oras_solve(self._ctx, _ptr(b), _ptr(out), nrhs, float(tol),
+                                          ct.byref(opts), ct.byref(info)), allow_warn=True)
+        return SolveResult(out, np.array(it[:]), np.array(rr[:]), np.array(cv[:], dtype=bool),
+                           info.t_solve, info.t_stencil, info.t_oras, info.t_ortho, info.cycles,
+                           info.total_iters, rc)
+
+    def point_sources(self, idx: Sequence[Sequence[int]], amp=None) -> torch.Tensor:
+        nrhs = len(idx)
+        ia = np.ascontiguousarray(np.asarray(idx, dtype=np.int32).reshape(nrhs, 3))
+        aa = None
+        if amp is not None:
+            a = np.asarray(amp, dtype=np.complex128).reshape(nrhs)
+            aa = np.ascontiguousarray(np.stack([a.real, a.imag], 1))
+        b = torch.empty((nrhs,) + self.shape, dtype=torch.complex128, device=self.device)
+        self._check(lib().oras_point_sources(self._ctx, ia.ctypes.data_as(ct.c_void_p),
+                                             None if aa is None else aa.ctypes.data_as(ct.c_void_p),
+                                             nrhs, _ptr(b)))
+        return b
+
+    def _rec(self, rec) -> torch.Tensor:
+        if isinstance(rec, torch.Tensor):
+            _need(rec, torch.int32, self.device, name="receivers")
+            return rec
+        return torch.as_tensor(np.asarray(rec, dtype=np.int32).reshape(-1, 3), device=self.device)
+
+    def sample(self, u: torch.Tensor, rec) -> torch.Tensor:
+        r = self._rec(rec)
+        nrhs = u.shape[0]
+        _need(u, torch.complex128, self.device, (nrhs,) + self.shape, name="u")
+        d = torch.empty((nrhs, r.shape[0]), dtype=torch.complex128, device=self.device)
+        self._check(lib().oras_sample(self._ctx, _ptr(u), nrhs, _ptr(r), r.shape[0], _ptr(d)))
+        return d
+
+    def spread(self, d: torch.Tensor, rec) -> torch.Tensor:
+        r = self._rec(rec)
+        nrhs = d.shape[0]
+        _need(d, torch.complex128, self.device, (nrhs, r.shape[0]), name="d")
+        b = torch.empty((nrhs,) + self.shape, dtype=torch.complex128, device=self.device)
+        self._check(lib().oras_spread(self._ctx, _ptr(d), nrhs, _ptr(r), r.shape[0], _ptr(b)))
+        return b
+
+    def gradient(self, u: torch.Tensor, mu: torch.Tensor) -> torch.Tensor:
+        nrhs = u.shape[0]
+        _need(u, torch.complex128, self.device, (nrhs,) + self.shape, name="u")
+        _need(mu, torch.complex128, self.device, u.shape, name="mu")
+        g = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        self._check(lib().oras_gradient(self._ctx, _ptr(u), _ptr(mu), nrhs, _ptr(g)))
+        return g
+
+    # -- test hooks ----------------------------------------------------------
+    def apply_A(self, x: torch.Tensor, prec: int = C128) -> torch.Tensor:
+        _need(x, torch.complex128, self.device, (x.shape[0],) + self.shape, name="x")
+        y = torch.empty_like(x)
+        self._check(lib().oras_apply_A(self._ctx, _ptr(x), _ptr(y), x.shape[0], int(prec)))
+        return y
+
+    def apply_M(self, x: torch.Tensor) -> torch.Tensor:
+        _need(x, torch.complex128, self.device, (x.shape[0],) + self.shape, name="x")
+        y = torch.empty_like(x)
+        self._check(lib().oras_apply_M(self._ctx, _ptr(x), _ptr(y), x.shape[0]))
+        return y
+
+    def coefficients(self) -> torch.Tensor:
+        out = torch.empty((27,) + self.shape, dtype=torch.complex128, device=self.device)
+        self._check(lib().oras_coefficients(self._ctx, _ptr(out)))
+        return out
+
+    def subdomains(self):
+        n = ct.c_int()
+        self._check(lib().oras_subdomain(self._ctx, 0, ct.byref(n), None))
+        out = []
+        for j in range(n.value):
+            b = (ct.c_int * 12)()
+            self._check(lib().oras_subdomain(self._ctx, j, None, b))
+            out.append(tuple(b[:]))
+        return out

@@ -1,0 +1,104 @@
+"""Parity of the HIP path with the oracle, element by element on seeded
+inputs (assembly, stencil, ORAS apply, sources, sampling, gradient)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import adjoint, operator as op, oras as ooras
+from paper_2110_15113_amd import workloads as wl
+
+from gpu_util import need_gpu, oracle_fields, rand_field, rel, say, setup, to_dev
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    dict(n=(13, 11, 12), npml=3, q=60.0, seed=1),
+    dict(n=(20, 17, 9), npml=2, q=None, seed=2),
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_assemble_coefficients(case):
+    need_gpu()
+    w = wl.small_random(case["n"], npml=case["npml"], q=case["q"], seed=case["seed"])
+    say(f"assemble {w.name}")
+    S = setup(w)
+    got = S.coefficients().cpu().numpy()
+    ref = op.row_coeffs(oracle_fields(w))
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    assert err < 1e-11, err
+
+
+@pytest.mark.parametrize("nrhs", [1, 3, 9])
+def test_apply_A_c128_and_c64(nrhs):
+    need_gpu()
+    w = wl.small_random((19, 13, 11), npml=3, q=80.0, seed=4)
+    say(f"apply_A nrhs={nrhs}")
+    S = setup(w, prec=1)          # complex64 stencil (plus the FP64 copy)
+    x = rand_field((w.nz, w.ny, w.nx), nrhs, 7)
+    C = op.row_coeffs(oracle_fields(w))
+    ref = op.apply_coeffs(C, x)
+    y128 = S.apply_A(to_dev(x, S), prec=2).cpu().numpy()
+    assert rel(y128, ref) < 1e-12
+    y64 = S.apply_A(to_dev(x, S), prec=1).cpu().numpy()
+    assert rel(y64, ref) < 2e-6
+
+
+ORAS_CASES = [
+    dict(n=(16, 16, 16), parts=(2, 2, 2), ov=2, npml=3, q=100.0, nrhs=2),
+    dict(n=(19, 17, 15), parts=(2, 3, 2), ov=1, npml=2, q=50.0, nrhs=3),
+    dict(n=(26, 14, 12), parts=(3, 1, 2), ov=3, npml=2, q=None, nrhs=9),
+    dict(n=(12, 12, 12), parts=(1, 1, 1), ov=2, npml=2, q=70.0, nrhs=1),
+]
+
+
+@pytest.mark.parametrize("case", ORAS_CASES)
+def test_apply_M_matches_oracle(case):
+    need_gpu()
+    w = wl.small_random(case["n"], npml=case["npml"], q=case["q"], seed=5,
+                        parts=case["parts"], overlap=case["ov"])
+    say(f"apply_M {case}")
+    F = oracle_fields(w)
+    M = ooras.ORAS(F, case["parts"], case["ov"])
+    x = rand_field((w.nz, w.ny, w.nx), case["nrhs"], 11)
+    ref = M.apply(x)
+    S = setup(w, prec=2, parts=case["parts"], overlap=case["ov"])
+    got = S.apply_M(to_dev(x, S)).cpu().numpy()
+    assert rel(got, ref) < 1e-9, rel(got, ref)
+    S64 = setup(w, prec=1, parts=case["parts"], overlap=case["ov"])
+    got64 = S64.apply_M(to_dev(x, S64)).cpu().numpy()
+    assert rel(got64, ref) < 1e-3, rel(got64, ref)
+
+
+def test_subdomain_boxes_match_oracle_partition():
+    need_gpu()
+    w = wl.small_random((19, 17, 15), npml=2, seed=3)
+    S = setup(w, parts=(2, 3, 2), overlap=2)
+    boxes = S.subdomains()
+    ref = ooras.partition((19, 17, 15), (2, 3, 2), 2)
+    assert len(boxes) == len(ref)
+    for b, r in zip(boxes, ref):
+        assert tuple(b[0:3]) == r.lo and tuple(b[3:6]) == r.hi
+        assert tuple(b[6:9]) == r.olo and tuple(b[9:12]) == r.ohi
+
+
+def test_sources_sample_spread_gradient():
+    need_gpu()
+    w = wl.small_random((14, 12, 10), npml=2, q=40.0, nsrc=3, seed=8)
+    say("sources/sample/spread/gradient")
+    S = setup(w)
+    F = oracle_fields(w)
+    amps = [1.0, 2.0 - 1.0j, 0.5j]
+    b = S.point_sources(w.sources, amps).cpu().numpy()
+    assert np.array_equal(b, op.point_sources(F, w.sources, amps))
+    rec = [(3, 3, 3), (5, 4, 3), (6, 5, 6), (3, 3, 3)]
+    U = rand_field((w.nz, w.ny, w.nx), 3, 1)
+    MU = rand_field((w.nz, w.ny, w.nx), 3, 2)
+    d = S.sample(to_dev(U, S), rec).cpu().numpy()
+    assert np.array_equal(d, adjoint.sample(U, rec))
+    G = rand_field((len(rec),), 3, 3).reshape(3, len(rec))
+    sp = S.spread(to_dev(G, S), rec).cpu().numpy()
+    assert np.abs(sp - adjoint.spread(G, rec, F.shape)).max() < 1e-15
+    g = S.gradient(to_dev(U, S), to_dev(MU, S)).cpu().numpy()
+    ref = adjoint.gradient(F, U, MU)
+    assert np.abs(g - ref).max() < 1e-11 * np.abs(ref).max()
