@@ -1,0 +1,252 @@
+"""Benchmark: ORAS-FGMRES Helmholtz solves on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 5] [--prec mixed|fp64]
+
+One step is the whole hot path over one block of right-hand sides of the
+workload: assemble the 27-point operator (a0), build and factor every
+subdomain matrix on the device (a1), and solve the block with ORAS-FGMRES to
+the workload's tolerance (stencil, restrict, plane substitutions,
+prolongation, Gram-Schmidt, Givens, cycle update, FP64 true residual).
+Inputs (velocity, Q, right-hand sides) are resident in HBM before timing.
+
+Prints one JSON line: RHS solved per second (value), the 27-point apply
+bandwidth, the roofline of the dominant kernel (the MFMA plane GEMM of the
+local substitutions, timed per launch with HIP events on the library's
+stream) and the CPU oracle baseline timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"hbm_GBps": 8000.0, "fp32_mfma_TFLOPs": 157.3, "fp64_mfma_TFLOPs": 78.6}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=5)
+    ap.add_argument("--prec", choices=["mixed", "fp64", "auto"], default="auto")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a device-to-device copy of MIB mebibytes (calibrates the "
+                         "HBM traffic counters) and exit")
+    return ap.parse_args()
+
+
+def copy_probe(mib: int):
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_MiB": mib, "bytes_read_per_copy": 4 * n,
+                      "bytes_written_per_copy": 4 * n}), flush=True)
+
+
+def kernel_source_hash() -> str:
+    with open(os.path.join(ROOT, "paper_2110_15113_amd", "csrc", "k_trisolve.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_for(workload: str, launches_bytes: float):
+    """HBM traffic per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "plane_gemm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    entry = rec.get(workload)
+    if not entry or entry.get("kernel_sha") != kernel_source_hash():
+        return None
+    return entry.get("bytes_per_launch")
+
+
+def cpu_baseline(w, nrhs, iters, t_budget=25.0):
+    """The oracle timed on a bounded sample of the same workload.
+
+    Sample: two interior subdomains of the workload (their Robin-cut local
+    matrices assembled and factored by the oracle, then one local solve on
+    the whole right-hand-side block), one 27-point apply and one CGS step on
+    a 40^3 window of the grid.  Extrapolated to the full solve as
+        T = N_sub * (setup + iters * solve) / 2 + iters * (n / 40^3) * (apply + cgs),
+    with the GPU run's Arnoldi step count."""
+    import numpy as np
+    from oracle import operator as op, oras as ooras
+
+    threads = os.cpu_count() or 1
+    F = op.make_fields(w.vel, w.Q, w.omega, w.h, w.npml)
+    subs = ooras.partition((w.nx, w.ny, w.nz), w.parts, w.overlap)
+    interior = [s for s in subs if all(s.lo[a] > 0 and s.hi[a] < (w.nx, w.ny, w.nz)[a]
+                                        for a in range(3))] or subs
+    pick = interior[:2]
+    rng = np.random.default_rng(0)
+    t0 = time.perf_counter()
+    t_setup = t_solve = 0.0
+    for s in pick:
+        a = time.perf_counter()
+        B = op.csr_from_coeffs(op.row_coeffs(F, s.lo, s.hi, restrict=True))
+        import scipy.sparse.linalg as spla
+        lu = spla.splu(B.tocsc())
+        b = time.perf_counter()
+        r = rng.normal(size=(B.shape[0], nrhs)) + 1j * rng.normal(size=(B.shape[0], nrhs))
+        lu.solve(r)
+        c = time.perf_counter()
+        t_setup += b - a
+        t_solve += c - b
+    win = 40
+    lo = (w.nx // 2 - win // 2, w.ny // 2 - win // 2, w.nz // 2 - win // 2)
+    hi = tuple(l + win for l in lo)
+    a = time.perf_counter()
+    C = op.row_coeffs(F, lo, hi)
+    x = rng.normal(size=(nrhs, win, win, win)) + 1j * rng.normal(size=(nrhs, win, win, win))
+    b_ = time.perf_counter()
+    op.apply_coeffs(C, x)
+    c = time.perf_counter()
+    V = x.reshape(nrhs, -1)
+    Vb = np.stack([V] * 10)
+    hh = np.einsum("jcn,cn->jc", Vb.conj(), V)
+    V = V - np.einsum("jcn,jc->cn", Vb, hh)
+    np.linalg.norm(V, axis=1)
+    d = time.perf_counter()
+    scale = w.n / win ** 3
+    nsub = len(subs)
+    T = nsub * (t_setup + iters * t_solve) / len(pick) + iters * scale * ((c - b_) + (d - c))
+    spent = time.perf_counter() - t0
+    return {"value": nrhs / T, "unit": "RHS/s", "cores": threads, "kind": "oracle",
+            "sample": (f"2 of {nsub} interior subdomains (oracle Robin-cut B_j assembly + SuperLU "
+                       f"factor + one {nrhs}-RHS local solve) and one 27-point apply + one "
+                       f"10-vector CGS step on a 40^3 window, extrapolated to {iters} Arnoldi "
+                       f"steps on the full grid; {spent:.1f} s of CPU work"),
+            "extrapolated_solve_s": T}
+
+
+def main():
+    args = parse()
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(1)
+    import numpy as np
+    import torch
+
+    from paper_2110_15113_amd import oras, workloads as wl
+
+    w = wl.CONFIGS[args.config]()
+    prec = args.prec
+    if prec == "auto":
+        prec = "mixed" if w.krylov_prec == "mixed" else "fp64"
+    P = oras.C64 if prec == "mixed" else oras.C128
+    dev = torch.device("cuda", 0)
+    vel = torch.as_tensor(w.vel, device=dev)
+    Q = None if w.Q is None else torch.as_tensor(w.Q, device=dev)
+    S = oras.Solver(0)
+    S.assemble(vel, w.h, w.npml, w.omega, Q, prec=P)
+    b = S.point_sources(w.sources)
+    nrhs = b.shape[0]
+    x = torch.empty_like(b)
+
+    def step():
+        S.assemble(vel, w.h, w.npml, w.omega, Q, prec=P)
+        S.factor(w.parts, w.overlap, P)
+        return S.solve(b, w.tol, restart=w.restart, maxit=w.maxit, out=x)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    if not args.no_profile:
+        S.profile(True)
+    results = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = step()
+        ta, tf = S.timings()
+        results.append((r, ta, tf))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    last, ta, tf = results[-1]
+    ok = bool(last.converged.all())
+    iters = int(last.total_iters)
+    # 27-point apply bandwidth: x in the stencil precision, y in complex128,
+    # 27 coefficients per node in the stencil precision
+    cb = 8 if P == oras.C64 else 16
+    s_pad = (nrhs + 7) // 8 * 8
+    sten_bytes = w.n * (s_pad * (cb + 16) + 27 * cb)
+    sten_GBps = sten_bytes * iters / last.t_stencil / 1e9 if last.t_stencil > 0 else None
+    roof = None
+    if not args.no_profile:
+        gs, gl, gf, gb = S.kernel_stats()
+        avg = gs / gl
+        flops_per = gf / gl
+        bytes_per = gb / gl
+        peak = PEAK["fp32_mfma_TFLOPs"] if P == oras.C64 else PEAK["fp64_mfma_TFLOPs"]
+        ach = flops_per / avg / 1e12
+        roof = {"kernel": "plane_gemm_kernel (MFMA 16x16x4, local substitutions)",
+                "bound": "mfma", "achieved": round(ach, 2), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(ach / peak, 4), "traffic": traffic_for(w.name, bytes_per),
+                "algorithmic_bytes_per_launch": bytes_per, "algorithmic_flops_per_launch": flops_per,
+                "avg_launch_us": avg * 1e6, "launches": gl,
+                "achieved_GBps": round(bytes_per / avg / 1e9, 1)}
+    rel_res = float(np.max(last.rel_res[:nrhs]))
+    out = {
+        "metric": "RHS solved/s to 1e-6 residual, mixed vs FP64 ORAS-FGMRES; 27-pt apply GB/s",
+        "value": nrhs * args.steps / elapsed,
+        "unit": "RHS/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64+c128" if P == oras.C64 else "c128",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: {w.nx}x{w.ny}x{w.nz} grid, h={w.h} m, "
+                               f"{w.freq} Hz, {nrhs} RHS, ORAS {w.parts[0]}x{w.parts[1]}x"
+                               f"{w.parts[2]} overlap {w.overlap}, "
+                               f"{'complex64 stencil+factors, FP64 FGMRES' if P == oras.C64 else 'all complex128'},"
+                               f" restart {w.restart}, tol {w.tol}",
+                   "nrhs": nrhs, "n": w.n, "tol": w.tol, "restart": w.restart,
+                   "precision": prec},
+        "converged": ok,
+        "max_rel_residual": rel_res,
+        "iterations": iters,
+        "cycles": int(last.cycles),
+        "t_assemble_s": ta,
+        "t_factor_s": tf,
+        "t_solve_s": last.t_solve,
+        "solve_only_RHS_per_s": nrhs / last.t_solve,
+        "t_stencil_s": last.t_stencil,
+        "t_oras_s": last.t_oras,
+        "t_ortho_s": last.t_ortho,
+        "stencil_GBps": sten_GBps,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        try:
+            out["cpu_baseline"] = cpu_baseline(w, nrhs, iters)
+        except Exception as e:  # the baseline is reported, never required
+            out["cpu_baseline"] = {"error": repr(e)}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -186,6 +186,18 @@ oras_status oras_apply_M(oras_ctx ctx, const void* x_dev, void* y_dev, int nrhs)
  * oras_factor_subdomains (the paper's set-up time T_f, sec. 3.2). */
 oras_status oras_timings(oras_ctx ctx, double* t_assemble, double* t_factor);
 
+/* Per-launch timing of the plane GEMM of the ORAS apply (the local
+ * forward/backward substitutions, sec. 2.2).  enable != 0 records a HIP
+ * event pair around every plane product on the context stream (the apply
+ * then synchronises once to read them) and resets the counters. */
+oras_status oras_profile(oras_ctx ctx, int enable);
+
+/* Accumulated plane-GEMM time (s), number of plane products, and their
+ * algorithmic work: 8 p^2 nrhs flops and p^2 + 2 p nrhs (+ p nrhs backward)
+ * complex entries moved per subdomain, p = plane size of its box. */
+oras_status oras_kernel_stats(oras_ctx ctx, double* gemm_seconds, long long* gemm_launches,
+                              double* gemm_flops, double* gemm_bytes);
+
 /* Copy the 27 FP64 stencil coefficients per node, layout (27, nz, ny, nx)
  * complex128, slot e = (ez+1)*9 + (ey+1)*3 + (ex+1). */
 oras_status oras_coefficients(oras_ctx ctx, void* out_dev);

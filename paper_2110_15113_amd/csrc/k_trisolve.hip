@@ -245,18 +245,29 @@ template <typename R, typename Z>
 void launch_oras_apply(const SubDesc* subs_dev, int nsub, int max_sz, int max_nt, long long max_p,
                        const C<R>* fac, const C<R>* lca, C<R>* ybuf, C<R>* tvbuf,
                        const double2* v, const double* scale, Z* z, int nx, int ny, int nz,
-                       int s, const int* owner_dev, int parts_x, int parts_y, hipStream_t st) {
+                       int s, const int* owner_dev, int parts_x, int parts_y, hipStream_t st,
+                       hipEvent_t* gemm_ev) {
   const int bs = 256;
+  int step = 0;
+  auto mark = [&](int which) {
+    if (gemm_ev) (void)hipEventRecord(gemm_ev[2 * step + which], st);
+  };
   const dim3 grhs((unsigned)((max_p * s + bs - 1) / bs), (unsigned)nsub);
   for (int k = 0; k < max_sz; ++k) {
     hipLaunchKernelGGL((fwd_rhs_kernel<R>), grhs, dim3(bs), 0, st, subs_dev, k, lca, ybuf, tvbuf,
                        v, scale, nx, ny, s);
+    mark(0);
     gemm_dispatch<R>(subs_dev, nsub, k, 0, max_nt, fac, ybuf, tvbuf, s, st);
+    mark(1);
+    ++step;
   }
   for (int k = max_sz - 2; k >= 0; --k) {
     hipLaunchKernelGGL((bwd_rhs_kernel<R>), grhs, dim3(bs), 0, st, subs_dev, k, lca, ybuf, tvbuf,
                        s);
+    mark(0);
     gemm_dispatch<R>(subs_dev, nsub, k, 1, max_nt, fac, ybuf, tvbuf, s, st);
+    mark(1);
+    ++step;
   }
   // owner map: owner_dev[0..nx) x part, [nx, nx+ny) y part, [nx+ny, ..) z part
   const long long n = (long long)nx * ny * nz;
@@ -267,15 +278,17 @@ void launch_oras_apply(const SubDesc* subs_dev, int nsub, int max_sz, int max_nt
 template void launch_oras_apply<float, float2>(const SubDesc*, int, int, int, long long,
                                                const float2*, const float2*, float2*, float2*,
                                                const double2*, const double*, float2*, int, int,
-                                               int, int, const int*, int, int, hipStream_t);
+                                               int, int, const int*, int, int, hipStream_t,
+                                               hipEvent_t*);
 template void launch_oras_apply<float, double2>(const SubDesc*, int, int, int, long long,
                                                 const float2*, const float2*, float2*, float2*,
                                                 const double2*, const double*, double2*, int,
-                                                int, int, int, const int*, int, int, hipStream_t);
+                                                int, int, int, const int*, int, int, hipStream_t,
+                                               hipEvent_t*);
 template void launch_oras_apply<double, double2>(const SubDesc*, int, int, int, long long,
                                                  const double2*, const double2*, double2*,
                                                  double2*, const double2*, const double*,
                                                  double2*, int, int, int, int, const int*, int,
-                                                 int, hipStream_t);
+                                                 int, hipStream_t, hipEvent_t*);
 
 }  // namespace oras

@@ -76,7 +76,7 @@ struct oras_ctx_s {
   int parts[3] = {1, 1, 1};
   int overlap = 0;
   std::vector<SubDesc> subs;
-  DevBuf subs_dev, fac, lca, owner, status;
+  DevBuf subs_dev, fac, tbuf, lca, owner, status;
   int max_sz = 0, max_nt = 0;
   long long max_p = 0, max_box = 0, y_rows = 0, tv_rows = 0;
   double t_factor = 0;
@@ -86,9 +86,20 @@ struct oras_ctx_s {
   long long ws_s = 0;
   int ws_m = 0;
 
-  ~oras_ctx_s() { release_all(); }
+  // optional per-launch timing of the plane GEMM (HIP events on the stream)
+  bool prof = false;
+  std::vector<hipEvent_t> gemm_ev;
+  std::vector<double> plane_p2_fwd, plane_p2_bwd, plane_p_fwd, plane_p_bwd;
+  double gemm_s = 0, gemm_flops = 0, gemm_bytes = 0;
+  long long gemm_launches = 0;
+
+  ~oras_ctx_s() {
+    release_all();
+    for (hipEvent_t e : gemm_ev) (void)hipEventDestroy(e);
+  }
   void release_factors() {
-    subs_dev.release(); fac.release(); lca.release(); owner.release(); status.release();
+    subs_dev.release(); fac.release(); tbuf.release(); lca.release(); owner.release();
+    status.release();
     ybuf.release(); tvbuf.release();
     subs.clear();
     factored = false;
@@ -215,30 +226,58 @@ oras_status ensure_oras_ws(oras_ctx c, long long s) {
 
 // z (internal, factor precision or c128 when z128) = M^{-1} (scale * v)
 oras_status oras_apply_internal(oras_ctx c, const double2* v, const double* scale, void* z, int s,
-                                bool z128) {
+                                bool z128, int nrhs) {
   TRY(ensure_oras_ws(c, s));
   const int* own = c->owner.as<int>();
+  const int nsteps = 2 * c->max_sz - 1;
+  hipEvent_t* ev = nullptr;
+  if (c->prof) {
+    while ((int)c->gemm_ev.size() < 2 * nsteps) {
+      hipEvent_t e;
+      HIP_TRY(c, hipEventCreate(&e));
+      c->gemm_ev.push_back(e);
+    }
+    ev = c->gemm_ev.data();
+  }
   if (c->factor_prec == ORAS_C64) {
     if (z128)
       launch_oras_apply<float, double2>(c->subs_dev.as<SubDesc>(), (int)c->subs.size(), c->max_sz,
                                         c->max_nt, c->max_p, c->fac.as<float2>(),
                                         c->lca.as<float2>(), c->ybuf.as<float2>(),
                                         c->tvbuf.as<float2>(), v, scale, (double2*)z, c->nx, c->ny,
-                                        c->nz, s, own, c->parts[0], c->parts[1], c->stream);
+                                        c->nz, s, own, c->parts[0], c->parts[1], c->stream, ev);
     else
       launch_oras_apply<float, float2>(c->subs_dev.as<SubDesc>(), (int)c->subs.size(), c->max_sz,
                                        c->max_nt, c->max_p, c->fac.as<float2>(),
                                        c->lca.as<float2>(), c->ybuf.as<float2>(),
                                        c->tvbuf.as<float2>(), v, scale, (float2*)z, c->nx, c->ny,
-                                       c->nz, s, own, c->parts[0], c->parts[1], c->stream);
+                                       c->nz, s, own, c->parts[0], c->parts[1], c->stream, ev);
   } else {
     launch_oras_apply<double, double2>(c->subs_dev.as<SubDesc>(), (int)c->subs.size(), c->max_sz,
                                        c->max_nt, c->max_p, c->fac.as<double2>(),
                                        c->lca.as<double2>(), c->ybuf.as<double2>(),
                                        c->tvbuf.as<double2>(), v, scale, (double2*)z, c->nx, c->ny,
-                                       c->nz, s, own, c->parts[0], c->parts[1], c->stream);
+                                       c->nz, s, own, c->parts[0], c->parts[1], c->stream, ev);
   }
   HIP_TRY(c, hipGetLastError());
+  if (ev) {
+    // per-launch durations and the algorithmic work of each plane step:
+    // 8 p^2 nrhs flops; p^2 matrix entries + t read + y written (+ y read backward)
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const double cs = (double)csize(c->factor_prec);
+    for (int st = 0; st < nsteps; ++st) {
+      float ms = 0;
+      HIP_TRY(c, hipEventElapsedTime(&ms, ev[2 * st], ev[2 * st + 1]));
+      const bool bwd = st >= c->max_sz;
+      const int k = bwd ? (c->max_sz - 2 - (st - c->max_sz)) : st;
+      const double p2 = bwd ? c->plane_p2_bwd[k] : c->plane_p2_fwd[k];
+      const double p1 = bwd ? c->plane_p_bwd[k] : c->plane_p_fwd[k];
+      c->gemm_s += ms * 1e-3;
+      c->gemm_flops += 8.0 * p2 * nrhs;
+      c->gemm_bytes += cs * (p2 + (bwd ? 3.0 : 2.0) * p1 * nrhs);
+      c->gemm_launches += 1;
+    }
+  }
   return ORAS_OK;
 }
 
@@ -316,6 +355,24 @@ oras_status oras_weight_table(double* out_host, int capacity, double* g0, double
   return ORAS_OK;
 }
 
+oras_status oras_profile(oras_ctx ctx, int enable) {
+  if (!ctx) return ORAS_E_ARG;
+  ctx->prof = enable != 0;
+  ctx->gemm_s = ctx->gemm_flops = ctx->gemm_bytes = 0;
+  ctx->gemm_launches = 0;
+  return ORAS_OK;
+}
+
+oras_status oras_kernel_stats(oras_ctx ctx, double* gemm_seconds, long long* gemm_launches,
+                              double* gemm_flops, double* gemm_bytes) {
+  if (!ctx) return ORAS_E_ARG;
+  if (gemm_seconds) *gemm_seconds = ctx->gemm_s;
+  if (gemm_launches) *gemm_launches = ctx->gemm_launches;
+  if (gemm_flops) *gemm_flops = ctx->gemm_flops;
+  if (gemm_bytes) *gemm_bytes = ctx->gemm_bytes;
+  return ORAS_OK;
+}
+
 oras_status oras_timings(oras_ctx ctx, double* t_assemble, double* t_factor) {
   if (!ctx) return ORAS_E_ARG;
   if (t_assemble) *t_assemble = ctx->t_assemble;
@@ -344,8 +401,14 @@ oras_status oras_assemble(oras_ctx c, const oras_grid* g, const double* vel_dev,
   const double t0 = now();
   const long long n = (long long)g->nx * g->ny * g->nz;
   const double need = (double)n * (7 * 8 + 16 * 2 + 27 * 16 + (stencil_prec == ORAS_C64 ? 27 * 8 : 0));
-  c->release_all();
-  TRY(check_free(c, need));
+  // buffers of an earlier assembly are reused when large enough
+  c->assembled = false;
+  c->factored = false;
+  {
+    const double held = (double)(c->w7.bytes + c->mt.bytes + c->qf.bytes + c->coef128.bytes +
+                                 c->coef64.bytes);
+    TRY(check_free(c, need - held));
+  }
   c->nx = g->nx;
   c->ny = g->ny;
   c->nz = g->nz;
@@ -472,9 +535,12 @@ oras_status oras_factor_subdomains(oras_ctx c, const int parts[3], int overlap, 
   const size_t cs = csize(factor_prec);
   const double need = (double)(fac_off + t_off + lca_off) * cs;
   TRY(check_device(c));
-  c->release_factors();
-  TRY(check_free(c, need));
-  DevBuf tbuf;
+  c->factored = false;
+  {
+    const double held = (double)(c->fac.bytes + c->tbuf.bytes + c->lca.bytes);
+    TRY(check_free(c, need - held));
+  }
+  DevBuf& tbuf = c->tbuf;
   TRY(dev_alloc(c, c->fac, (size_t)fac_off * cs));
   oras_status st = dev_alloc(c, tbuf, (size_t)t_off * cs);
   if (st != ORAS_OK) { c->release_factors(); return st; }
@@ -509,7 +575,6 @@ oras_status oras_factor_subdomains(oras_ctx c, const int parts[3], int overlap, 
                                   c->status.as<int>(), c->stream);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
-      tbuf.release();
       c->release_factors();
       return fail(c, ORAS_E_HIP, std::string("factor launch: ") + hipGetErrorString(e));
     }
@@ -518,13 +583,25 @@ oras_status oras_factor_subdomains(oras_ctx c, const int parts[3], int overlap, 
   HIP_TRY(c, hipMemcpyAsync(stat.data(), c->status.p, stat.size() * sizeof(int),
                             hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  tbuf.release();
   c->t_factor = now() - t0;
   for (size_t j = 0; j < stat.size(); ++j)
     if (stat[j]) {
       c->release_factors();
       return fail(c, ORAS_E_NUMERIC,
                   "zero or non-finite pivot while factoring subdomain " + std::to_string(j));
+    }
+  c->plane_p2_fwd.assign(max_sz, 0.0);
+  c->plane_p2_bwd.assign(max_sz, 0.0);
+  c->plane_p_fwd.assign(max_sz, 0.0);
+  c->plane_p_bwd.assign(max_sz, 0.0);
+  for (const SubDesc& d : subs)
+    for (int k = 0; k < d.sz; ++k) {
+      c->plane_p2_fwd[k] += (double)d.p * d.p;
+      c->plane_p_fwd[k] += d.p;
+      if (k <= d.sz - 2) {
+        c->plane_p2_bwd[k] += (double)d.p * d.p;
+        c->plane_p_bwd[k] += d.p;
+      }
     }
   c->subs = subs;
   c->factor_prec = factor_prec;
@@ -588,7 +665,7 @@ oras_status oras_apply_M(oras_ctx c, const void* x_dev, void* y_dev, int nrhs) {
   TRY(dev_alloc(c, c->Bint, (size_t)(c->n * s) * sizeof(double2)));
   TRY(dev_alloc(c, c->Tmp, (size_t)(c->n * s) * sizeof(double2)));
   launch_to_internal((const double2*)x_dev, c->Bint.as<double2>(), c->n, nrhs, (int)s, 0, c->stream);
-  TRY(oras_apply_internal(c, c->Bint.as<double2>(), nullptr, c->Tmp.p, (int)s, true));
+  TRY(oras_apply_internal(c, c->Bint.as<double2>(), nullptr, c->Tmp.p, (int)s, true, nrhs));
   launch_from_internal(c->Tmp.as<double2>(), (double2*)y_dev, c->n, nrhs, (int)s, 0, c->stream);
   HIP_TRY(c, hipGetLastError());
   HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -717,7 +794,7 @@ oras_status oras_solve(oras_ctx c, const void* b_dev, void* x_dev, int nrhs, dou
       double2* Vj = V + (size_t)j * ns;
       double2* Vn = V + (size_t)(j + 1) * ns;
       HIP_TRY(c, hipEventRecord(ev[0], st));
-      TRY(oras_apply_internal(c, Vj, scale + j * s, Zj, (int)s, !mixed));
+      TRY(oras_apply_internal(c, Vj, scale + j * s, Zj, (int)s, !mixed, nrhs));
       HIP_TRY(c, hipEventRecord(ev[1], st));
       if (mixed)
         launch_stencil<float>(c->coef64.as<float2>(), (const float2*)Zj, nullptr, Vn, c->nx, c->ny,

@@ -107,7 +107,8 @@ template <typename R, typename Z>
 void launch_oras_apply(const SubDesc* subs_dev, int nsub, int max_sz, int max_nt, long long max_p,
                        const C<R>* fac, const C<R>* lca, C<R>* ybuf, C<R>* tvbuf,
                        const double2* v, const double* scale, Z* z, int nx, int ny, int nz,
-                       int s, const int* owner_dev, int parts_x, int parts_y, hipStream_t st);
+                       int s, const int* owner_dev, int parts_x, int parts_y, hipStream_t st,
+                       hipEvent_t* gemm_ev = nullptr);
 
 // Krylov helpers
 void launch_to_internal(const double2* src, double2* dst, long long n, int nrhs, int s, int conj,

@@ -79,6 +79,10 @@ SIGNATURES = {
     "oras_apply_A": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_int]),
     "oras_apply_M": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int]),
     "oras_timings": (ct.c_int, [ct.c_void_p, ct.POINTER(ct.c_double), ct.POINTER(ct.c_double)]),
+    "oras_profile": (ct.c_int, [ct.c_void_p, ct.c_int]),
+    "oras_kernel_stats": (ct.c_int, [ct.c_void_p, ct.POINTER(ct.c_double),
+                                     ct.POINTER(ct.c_longlong), ct.POINTER(ct.c_double),
+                                     ct.POINTER(ct.c_double)]),
     "oras_coefficients": (ct.c_int, [ct.c_void_p, ct.c_void_p]),
     "oras_subdomain": (ct.c_int, [ct.c_void_p, ct.c_int, ct.POINTER(ct.c_int),
                                   ct.POINTER(ct.c_int)]),
@@ -209,6 +213,19 @@ class Solver:
         ta, tf = ct.c_double(), ct.c_double()
         self._check(lib().oras_timings(self._ctx, ct.byref(ta), ct.byref(tf)))
         return ta.value, tf.value
+
+    def profile(self, enable: bool = True):
+        """Time every plane GEMM of the ORAS apply with HIP events (resets)."""
+        self._check(lib().oras_profile(self._ctx, int(bool(enable))))
+
+    def kernel_stats(self):
+        """(seconds, launches, algorithmic flops, algorithmic bytes) of the
+        plane GEMM since the last profile() call."""
+        s, f, b = ct.c_double(), ct.c_double(), ct.c_double()
+        n = ct.c_longlong()
+        self._check(lib().oras_kernel_stats(self._ctx, ct.byref(s), ct.byref(n), ct.byref(f),
+                                            ct.byref(b)))
+        return s.value, n.value, f.value, b.value
 
     # -- solve -------------------------------------------------------------
     def solve(self, b: torch.Tensor, tol: float, restart: int = 30, maxit: int = 1000,
