@@ -64,13 +64,28 @@ __global__ void colnorm2_kernel(const double2* __restrict__ x, long long n, int 
   block_reduce_store(lds, acc, s, G, partial + (long long)blockIdx.x * s + c);
 }
 
-__global__ void finish_norm_kernel(const double* __restrict__ partial, int nblk, int s,
-                                   double* __restrict__ out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= s) return;
+// Fixed-order tree sum of 256 per-thread values (deterministic).
+__device__ inline double tree_sum(double* lds, double v) {
+  __syncthreads();   // earlier readers of lds are done
+  lds[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) lds[threadIdx.x] += lds[threadIdx.x + w];
+    __syncthreads();
+  }
+  return lds[0];
+}
+
+// out[c] = sqrt(sum over blocks of partial[blk][c]); one work-group per column
+__global__ void __launch_bounds__(256) finish_norm_kernel(const double* __restrict__ partial,
+                                                          int nblk, int s,
+                                                          double* __restrict__ out) {
+  __shared__ double lds[256];
+  const int c = blockIdx.x;
   double acc = 0.0;
-  for (int b = 0; b < nblk; ++b) acc += partial[(long long)b * s + c];
-  out[c] = sqrt(acc);
+  for (int b = threadIdx.x; b < nblk; b += 256) acc += partial[(long long)b * s + c];
+  const double t = tree_sum(lds, acc);
+  if (threadIdx.x == 0) out[c] = sqrt(t);
 }
 
 // partial[blk][i][c] = sum_nodes conj(V_i) w   for i < j1   (scale applied later)
@@ -114,18 +129,25 @@ __global__ void cgs_dot_kernel(const double2* __restrict__ V, long long vstride,
 }
 
 // h[i][c] = scale[i][c] * sum_blk partial   (i < j1); hs = h * scale (for the update)
-__global__ void cgs_finish_dot_kernel(const double2* __restrict__ partial, int nblk, int j1, int s,
-                                      const double* __restrict__ scale, double2* __restrict__ h,
-                                      double2* __restrict__ hs) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= j1 * s) return;
+// one work-group per (i, c), fixed-order tree over the block partials
+__global__ void __launch_bounds__(256)
+cgs_finish_dot_kernel(const double2* __restrict__ partial, int nblk, int j1, int s,
+                      const double* __restrict__ scale, double2* __restrict__ h,
+                      double2* __restrict__ hs) {
+  __shared__ double lds[256];
+  const int idx = blockIdx.x;
   const int i = idx / s, c = idx % s;
   double2 acc = make_double2(0.0, 0.0);
-  for (int b = 0; b < nblk; ++b) acc = cadd(acc, partial[((long long)b * j1 + i) * s + c]);
-  const double sc = scale[idx];
-  acc = cscale(acc, sc);
-  h[idx] = acc;
-  hs[idx] = cscale(acc, sc);
+  for (int b = threadIdx.x; b < nblk; b += 256)
+    acc = cadd(acc, partial[((long long)b * j1 + i) * s + c]);
+  const double re = tree_sum(lds, acc.x);
+  const double imv = tree_sum(lds, acc.y);
+  if (threadIdx.x == 0) {
+    const double sc = scale[idx];
+    const double2 v = make_double2(re * sc, imv * sc);
+    h[idx] = v;
+    hs[idx] = cscale(v, sc);
+  }
 }
 
 // w -= sum_i V_i hs_i ; partial[blk][c] = sum |w|^2
@@ -152,16 +174,14 @@ __global__ void cgs_update_kernel(const double2* __restrict__ V, long long vstri
 
 // One Arnoldi step per column: H column j, Givens rotation, residual estimate.
 // H[(i * m + j) * s + c] for row i in 0..m, column j in 0..m-1.
-__global__ void arnoldi_step_kernel(int j, int m, int s, const double* __restrict__ norm_partial,
-                                    int nblk, const double2* __restrict__ h, double2* H,
-                                    double* cs, double2* sn, double2* g, double* scale_next,
-                                    int* jc, int* done, const double* __restrict__ bnorm,
-                                    double tol, double* est) {
+__global__ void arnoldi_step_kernel(int j, int m, int s, const double* __restrict__ hnorm,
+                                    const double2* __restrict__ h, double2* H, double* cs,
+                                    double2* sn, double2* g, double* scale_next, int* jc,
+                                    int* done, const double* __restrict__ bnorm, double tol,
+                                    double* est) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= s) return;
-  double nn = 0.0;
-  for (int b = 0; b < nblk; ++b) nn += norm_partial[(long long)b * s + c];
-  const double hn = sqrt(nn);
+  const double hn = hnorm[c];
   if (done[c]) {
     scale_next[c] = 0.0;
     return;
@@ -380,8 +400,7 @@ void launch_colnorm2(const double2* x, long long n, int s, double* partial, int 
   hipLaunchKernelGGL(colnorm2_kernel, dim3(nblk), dim3(group_threads(s)), 0, st, x, n, s, partial);
 }
 void launch_finish_norm(const double* partial, int nblk, int s, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(finish_norm_kernel, dim3(blocks_for(s, 64)), dim3(64), 0, st, partial, nblk, s,
-                     out);
+  hipLaunchKernelGGL(finish_norm_kernel, dim3(s), dim3(256), 0, st, partial, nblk, s, out);
 }
 void launch_cgs_dot(const double2* V, long long vstride, int j1, const double2* w, long long n,
                     int s, double2* partial, int nblk, hipStream_t st) {
@@ -390,20 +409,20 @@ void launch_cgs_dot(const double2* V, long long vstride, int j1, const double2* 
 }
 void launch_cgs_finish_dot(const double2* partial, int nblk, int j1, int s, const double* scale,
                            double2* h, double2* hs, hipStream_t st) {
-  hipLaunchKernelGGL(cgs_finish_dot_kernel, dim3(blocks_for((long long)j1 * s, 64)), dim3(64), 0,
-                     st, partial, nblk, j1, s, scale, h, hs);
+  hipLaunchKernelGGL(cgs_finish_dot_kernel, dim3(j1 * s), dim3(256), 0, st, partial, nblk, j1, s,
+                     scale, h, hs);
 }
 void launch_cgs_update(const double2* V, long long vstride, int j1, const double2* hs, double2* w,
                        long long n, int s, double* partial, int nblk, hipStream_t st) {
   hipLaunchKernelGGL(cgs_update_kernel, dim3(nblk), dim3(group_threads(s)), 0, st, V, vstride, j1,
                      hs, w, n, s, partial);
 }
-void launch_arnoldi_step(int j, int m, int s, const double* norm_partial, int nblk,
-                         const double2* h, double2* H, double* cs, double2* sn, double2* g,
-                         double* scale_next, int* jc, int* done, const double* bnorm, double tol,
-                         double* est, hipStream_t st) {
-  hipLaunchKernelGGL(arnoldi_step_kernel, dim3(blocks_for(s, 64)), dim3(64), 0, st, j, m, s,
-                     norm_partial, nblk, h, H, cs, sn, g, scale_next, jc, done, bnorm, tol, est);
+void launch_arnoldi_step(int j, int m, int s, const double* hnorm, const double2* h, double2* H,
+                         double* cs, double2* sn, double2* g, double* scale_next, int* jc,
+                         int* done, const double* bnorm, double tol, double* est,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(arnoldi_step_kernel, dim3(blocks_for(s, 64)), dim3(64), 0, st, j, m, s, hnorm,
+                     h, H, cs, sn, g, scale_next, jc, done, bnorm, tol, est);
 }
 void launch_cycle_init(int s, int m, const double* beta, const int* conv, double2* g,
                        double* scale0, int* jc, int* done, hipStream_t st) {

@@ -76,7 +76,8 @@ struct oras_ctx_s {
   int parts[3] = {1, 1, 1};
   int overlap = 0;
   std::vector<SubDesc> subs;
-  DevBuf subs_dev, fac, tbuf, lca, owner, status;
+  DevBuf subs_dev, fac, tbuf, lca, status;
+  OrasPlan plan;
   int max_sz = 0, max_nt = 0;
   long long max_p = 0, max_box = 0, y_rows = 0, tv_rows = 0;
   double t_factor = 0;
@@ -98,7 +99,8 @@ struct oras_ctx_s {
     for (hipEvent_t e : gemm_ev) (void)hipEventDestroy(e);
   }
   void release_factors() {
-    subs_dev.release(); fac.release(); tbuf.release(); lca.release(); owner.release();
+    subs_dev.release(); fac.release(); tbuf.release(); lca.release();
+    plan = OrasPlan();
     status.release();
     ybuf.release(); tvbuf.release();
     subs.clear();
@@ -228,7 +230,6 @@ oras_status ensure_oras_ws(oras_ctx c, long long s) {
 oras_status oras_apply_internal(oras_ctx c, const double2* v, const double* scale, void* z, int s,
                                 bool z128, int nrhs) {
   TRY(ensure_oras_ws(c, s));
-  const int* own = c->owner.as<int>();
   const int nsteps = 2 * c->max_sz - 1;
   hipEvent_t* ev = nullptr;
   if (c->prof) {
@@ -239,25 +240,20 @@ oras_status oras_apply_internal(oras_ctx c, const double2* v, const double* scal
     }
     ev = c->gemm_ev.data();
   }
+  const OrasPlan& pl = c->plan;
   if (c->factor_prec == ORAS_C64) {
     if (z128)
-      launch_oras_apply<float, double2>(c->subs_dev.as<SubDesc>(), (int)c->subs.size(), c->max_sz,
-                                        c->max_nt, c->max_p, c->fac.as<float2>(),
-                                        c->lca.as<float2>(), c->ybuf.as<float2>(),
-                                        c->tvbuf.as<float2>(), v, scale, (double2*)z, c->nx, c->ny,
-                                        c->nz, s, own, c->parts[0], c->parts[1], c->stream, ev);
+      launch_oras_apply<float, double2>(pl, c->fac.as<float2>(), c->lca.as<float2>(),
+                                        c->ybuf.as<float2>(), c->tvbuf.as<float2>(), v, scale,
+                                        (double2*)z, c->nx, c->ny, s, c->stream, ev);
     else
-      launch_oras_apply<float, float2>(c->subs_dev.as<SubDesc>(), (int)c->subs.size(), c->max_sz,
-                                       c->max_nt, c->max_p, c->fac.as<float2>(),
-                                       c->lca.as<float2>(), c->ybuf.as<float2>(),
-                                       c->tvbuf.as<float2>(), v, scale, (float2*)z, c->nx, c->ny,
-                                       c->nz, s, own, c->parts[0], c->parts[1], c->stream, ev);
+      launch_oras_apply<float, float2>(pl, c->fac.as<float2>(), c->lca.as<float2>(),
+                                       c->ybuf.as<float2>(), c->tvbuf.as<float2>(), v, scale,
+                                       (float2*)z, c->nx, c->ny, s, c->stream, ev);
   } else {
-    launch_oras_apply<double, double2>(c->subs_dev.as<SubDesc>(), (int)c->subs.size(), c->max_sz,
-                                       c->max_nt, c->max_p, c->fac.as<double2>(),
-                                       c->lca.as<double2>(), c->ybuf.as<double2>(),
-                                       c->tvbuf.as<double2>(), v, scale, (double2*)z, c->nx, c->ny,
-                                       c->nz, s, own, c->parts[0], c->parts[1], c->stream, ev);
+    launch_oras_apply<double, double2>(pl, c->fac.as<double2>(), c->lca.as<double2>(),
+                                       c->ybuf.as<double2>(), c->tvbuf.as<double2>(), v, scale,
+                                       (double2*)z, c->nx, c->ny, s, c->stream, ev);
   }
   HIP_TRY(c, hipGetLastError());
   if (ev) {
@@ -546,19 +542,9 @@ oras_status oras_factor_subdomains(oras_ctx c, const int parts[3], int overlap, 
   if (st != ORAS_OK) { c->release_factors(); return st; }
   TRY(dev_alloc(c, c->lca, (size_t)lca_off * cs));
   TRY(dev_alloc(c, c->subs_dev, subs.size() * sizeof(SubDesc)));
-  TRY(dev_alloc(c, c->owner, (size_t)(nn[0] + nn[1] + nn[2]) * sizeof(int)));
   TRY(dev_alloc(c, c->status, subs.size() * sizeof(int)));
-  std::vector<int> own;
-  for (int a = 0; a < 3; ++a)
-    for (int i = 0; i < nn[a]; ++i) {
-      int t = 0;
-      while (!(cuts[a][t] <= i && i < cuts[a][t + 1])) ++t;
-      own.push_back(t);
-    }
   HIP_TRY(c, hipMemcpyAsync(c->subs_dev.p, subs.data(), subs.size() * sizeof(SubDesc),
                             hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(c->owner.p, own.data(), own.size() * sizeof(int), hipMemcpyHostToDevice,
-                            c->stream));
   launch_zero(c->status.p, subs.size() * sizeof(int), c->stream);
   const double t0 = now();
   launch_assemble_local(opview(c), c->subs_dev.as<SubDesc>(), (int)subs.size(), max_box, c->lca.p,
@@ -615,6 +601,11 @@ oras_status oras_factor_subdomains(oras_ctx c, const int parts[3], int overlap, 
   c->max_box = max_box;
   c->y_rows = y_rows;
   c->tv_rows = tv_rows;
+  c->plan.subs = c->subs_dev.as<SubDesc>();
+  c->plan.nsub = (int)subs.size();
+  c->plan.max_sz = max_sz;
+  c->plan.max_nt = max_nt;
+  c->plan.max_p = max_p;
   c->factored = true;
   return ORAS_OK;
 }
@@ -740,6 +731,7 @@ oras_status oras_solve(oras_ctx c, const void* b_dev, void* x_dev, int nrhs, dou
   double* bnorm = (double*)carve(sizeof(double) * s);
   double* beta = (double*)carve(sizeof(double) * s);
   double* est = (double*)carve(sizeof(double) * s);
+  double* hnorm = (double*)carve(sizeof(double) * s);
   int* jc = (int*)carve(sizeof(int) * s);
   int* done = (int*)carve(sizeof(int) * s);
   int* conv_d = (int*)carve(sizeof(int) * s);
@@ -806,8 +798,9 @@ oras_status oras_solve(oras_ctx c, const void* b_dev, void* x_dev, int nrhs, dou
       launch_cgs_dot(V, ns, j + 1, Vn, n, (int)s, dpart, nblk, st);
       launch_cgs_finish_dot(dpart, nblk, j + 1, (int)s, scale, hv, hs, st);
       launch_cgs_update(V, ns, j + 1, hs, Vn, n, (int)s, npart, nblk, st);
-      launch_arnoldi_step(j, m, (int)s, npart, nblk, hv, H, cs, sn, g, scale + (j + 1) * s, jc,
-                          done, bnorm, tol, est, st);
+      launch_finish_norm(npart, nblk, (int)s, hnorm, st);
+      launch_arnoldi_step(j, m, (int)s, hnorm, hv, H, cs, sn, g, scale + (j + 1) * s, jc, done,
+                          bnorm, tol, est, st);
       HIP_TRY(c, hipEventRecord(ev[3], st));
       HIP_TRY(c, hipGetLastError());
       for (long long col = 0; col < s; ++col)

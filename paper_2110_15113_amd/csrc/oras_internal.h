@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 #include "../../include/oras.h"
 
@@ -101,14 +102,23 @@ template <typename R>
 void launch_factor_plane(const SubDesc* subs_dev, int nsub, int k, int max_nt, C<R>* fac,
                          C<R>* tbuf, const C<R>* lca, int* status, hipStream_t st);
 
+// Shape of the ORAS apply: the 2 max_sz - 1 plane steps (forward k = 0..,
+// then backward k = max_sz - 2..0) over the subdomain descriptors.
+struct OrasPlan {
+  const SubDesc* subs = nullptr;   // device
+  int nsub = 0;
+  int max_sz = 0;
+  int max_nt = 0;
+  long long max_p = 0;
+};
+
 // Tri-solve (ORAS apply).  Input v (double2, global [n][s]) times per-column scale
-// (may be null) -> output z (global [n][s], precision Z).
+// (may be null) -> output z (global [n][s], precision Z).  gemm_ev (2 per step,
+// or null) brackets every plane GEMM with HIP events.
 template <typename R, typename Z>
-void launch_oras_apply(const SubDesc* subs_dev, int nsub, int max_sz, int max_nt, long long max_p,
-                       const C<R>* fac, const C<R>* lca, C<R>* ybuf, C<R>* tvbuf,
-                       const double2* v, const double* scale, Z* z, int nx, int ny, int nz,
-                       int s, const int* owner_dev, int parts_x, int parts_y, hipStream_t st,
-                       hipEvent_t* gemm_ev = nullptr);
+void launch_oras_apply(const OrasPlan& plan, const C<R>* fac, const C<R>* lca, C<R>* ybuf,
+                       C<R>* tvbuf, const double2* v, const double* scale, Z* z, int nx, int ny,
+                       int s, hipStream_t st, hipEvent_t* gemm_ev = nullptr);
 
 // Krylov helpers
 void launch_to_internal(const double2* src, double2* dst, long long n, int nrhs, int s, int conj,
@@ -123,10 +133,10 @@ void launch_cgs_finish_dot(const double2* partial, int nblk, int j1, int s, cons
                            double2* h, double2* hs, hipStream_t st);
 void launch_cgs_update(const double2* V, long long vstride, int j1, const double2* hs, double2* w,
                        long long n, int s, double* partial, int nblk, hipStream_t st);
-void launch_arnoldi_step(int j, int m, int s, const double* norm_partial, int nblk,
-                         const double2* h, double2* H, double* cs, double2* sn, double2* g,
-                         double* scale_next, int* jc, int* done, const double* bnorm, double tol,
-                         double* est, hipStream_t st);
+void launch_arnoldi_step(int j, int m, int s, const double* hnorm, const double2* h, double2* H,
+                         double* cs, double2* sn, double2* g, double* scale_next, int* jc,
+                         int* done, const double* bnorm, double tol, double* est,
+                         hipStream_t st);
 void launch_cycle_init(int s, int m, const double* beta, const int* conv, double2* g,
                        double* scale0, int* jc, int* done, hipStream_t st);
 void launch_backsolve(int m, int s, const double2* H, const double2* g, const int* jc, double2* y,
