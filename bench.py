@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--prec", choices=["mixed", "fp64", "auto"], default="auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the all-FP64 run of the same workload (mixed precision only)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB mebibytes (calibrates the "
                          "HBM traffic counters) and exit")
@@ -240,6 +242,35 @@ def main():
         "stencil_GBps": sten_GBps,
         "roofline": roof,
     }
+    if P == oras.C64 and not args.no_compare:
+        # the same workload, same step, all complex128, in a fresh context
+        x_mixed = x.clone()
+        S.close()
+        del S
+        torch.cuda.empty_cache()
+        S2 = oras.Solver(0)
+
+        def step64():
+            S2.assemble(vel, w.h, w.npml, w.omega, Q, prec=oras.C128)
+            S2.factor(w.parts, w.overlap, oras.C128)
+            return S2.solve(b, w.tol, restart=w.restart, maxit=w.maxit, out=x)
+
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        r64 = step64()
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - a
+        _, tf64 = S2.timings()
+        err = (torch.linalg.vector_norm((x_mixed - x).reshape(-1))
+               / torch.linalg.vector_norm(x.reshape(-1))).item()
+        out["fp64_same_workload"] = {
+            "ms_per_step": t64 * 1e3, "t_factor_s": tf64, "t_solve_s": r64.t_solve,
+            "iterations": int(r64.total_iters), "converged": bool(r64.converged.all()),
+            "RHS_per_s": nrhs / t64}
+        out["mixed_speedup_step"] = t64 / (elapsed / args.steps)
+        out["mixed_speedup_solve"] = r64.t_solve / last.t_solve
+        out["rel_L2_mixed_vs_fp64"] = err
+        S2.close()
     if not args.no_cpu_baseline:
         try:
             out["cpu_baseline"] = cpu_baseline(w, nrhs, iters)

@@ -1,0 +1,147 @@
+"""Full-size workloads in the launch configuration the benchmark times.
+
+The oracle cannot solve these sizes, so it checks sampled outputs and
+properties that hold at any size:
+  * the 27 coefficients of sampled rows (windows in the PML, the interior and
+    a corner) against the oracle's assembly;
+  * the true residual of the GPU solution meets tol, and the GPU residual
+    b - A x equals the oracle's residual on the sampled windows;
+  * the local solve of one interior subdomain: the ORAS apply at that
+    subdomain's owned nodes equals the oracle's direct solve with its B_j;
+  * mixed precision: the solution at tol 1e-6 is within 1e-4 (relative L2) of
+    the FP64 GPU solution at tol 1e-10 (whose residual is certified above).
+"""
+import gc
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import direct, operator as op, oras as ooras
+from paper_2110_15113_amd import workloads as wl
+
+from gpu_util import need_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _solver(w, prec):
+    from paper_2110_15113_amd import oras
+    S = oras.Solver(0)
+    vel = torch.as_tensor(w.vel, device=S.device)
+    Q = None if w.Q is None else torch.as_tensor(w.Q, device=S.device)
+    S.assemble(vel, w.h, w.npml, w.omega, Q, prec=prec)
+    S.factor(w.parts, w.overlap, prec)
+    return S
+
+
+def _windows(w):
+    e = 5
+    return [(0, 0, 0), (w.nx // 2 - 2, w.ny // 2 - 3, w.nz // 2 - 1),
+            (w.nx - e, w.ny // 3, w.npml - 2)]
+
+
+def _check_coefficients(S, F, w):
+    C = S.coefficients()
+    for lo in _windows(w):
+        hi = tuple(min(l + 5, n) for l, n in zip(lo, (w.nx, w.ny, w.nz)))
+        ref = op.row_coeffs(F, lo, hi)
+        got = C[:, lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]].cpu().numpy()
+        assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max(), lo
+    del C
+
+
+def _check_residual(S, F, w, b, x, tol):
+    r = b - S.apply_A(x)
+    rn = torch.linalg.vector_norm(r.reshape(r.shape[0], -1), dim=1)
+    bn = torch.linalg.vector_norm(b.reshape(b.shape[0], -1), dim=1)
+    assert bool((rn <= tol * bn * 1.0001).all()), (rn / bn).max().item()
+    for lo in _windows(w):
+        hi = tuple(min(l + 5, n) for l, n in zip(lo, (w.nx, w.ny, w.nz)))
+        C = op.row_coeffs(F, lo, hi)
+        # x on the window grown by one node (zero outside the grid)
+        glo = [max(l - 1, 0) for l in lo]
+        ghi = [min(h + 1, n) for h, n in zip(hi, (w.nx, w.ny, w.nz))]
+        xw = x[:2, glo[2]:ghi[2], glo[1]:ghi[1], glo[0]:ghi[0]].cpu().numpy()
+        pad = np.zeros((2, hi[2] - lo[2] + 2, hi[1] - lo[1] + 2, hi[0] - lo[0] + 2), complex)
+        o = [glo[a] - (lo[a] - 1) for a in range(3)]
+        pad[:, o[2]:o[2] + xw.shape[1], o[1]:o[1] + xw.shape[2], o[0]:o[0] + xw.shape[3]] = xw
+        Ax = np.zeros((2, hi[2] - lo[2], hi[1] - lo[1], hi[0] - lo[0]), complex)
+        for ei, (ex, ey, ez) in enumerate(op.OFFSETS):
+            Ax += C[ei] * pad[:, 1 + ez:pad.shape[1] - 1 + ez, 1 + ey:pad.shape[2] - 1 + ey,
+                              1 + ex:pad.shape[3] - 1 + ex]
+        rw = b[:2, lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]].cpu().numpy() - Ax
+        rg = r[:2, lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]].cpu().numpy()
+        scale = float(bn[:2].max()) + 1e-300
+        assert np.abs(rw - rg).max() <= 1e-11 * scale, lo
+
+
+def _check_local_solve(S, F, w, tol_rel):
+    subs = ooras.partition((w.nx, w.ny, w.nz), w.parts, w.overlap)
+    inner = [s for s in subs if all(s.lo[a] > 0 and s.hi[a] < (w.nx, w.ny, w.nz)[a]
+                                    for a in range(3))] or subs
+    s = inner[len(inner) // 2]
+    rng = np.random.default_rng(1)
+    v = rng.normal(size=(2, w.nz, w.ny, w.nx)) + 1j * rng.normal(size=(2, w.nz, w.ny, w.nx))
+    z = S.apply_M(torch.as_tensor(v, device=S.device)).cpu().numpy()
+    bs = tuple(s.hi[a] - s.lo[a] for a in range(3))
+    B = op.csr_from_coeffs(op.row_coeffs(F, s.lo, s.hi, restrict=True))
+    lu = direct.BlockTridiagLU(B, bs[0] * bs[1], bs[2])
+    box = (slice(None),) + tuple(slice(s.lo[a], s.hi[a]) for a in (2, 1, 0))
+    y = lu.solve(v[box].reshape(2, -1).T).T.reshape((2, bs[2], bs[1], bs[0]))
+    own = (slice(None),) + tuple(slice(s.olo[a] - s.lo[a], s.ohi[a] - s.lo[a]) for a in (2, 1, 0))
+    dst = (slice(None),) + tuple(slice(s.olo[a], s.ohi[a]) for a in (2, 1, 0))
+    err = np.linalg.norm(z[dst] - y[own]) / np.linalg.norm(y[own])
+    assert err <= tol_rel, err
+
+
+@pytest.mark.parametrize("cfg", [2, 4])
+def test_fp64_workload(cfg):
+    need_gpu()
+    from paper_2110_15113_amd import oras
+    w = wl.CONFIGS[cfg]()
+    say(f"full-size config {cfg}")
+    F = op.make_fields(w.vel, w.Q, w.omega, w.h, w.npml)
+    S = _solver(w, oras.C128)
+    _check_coefficients(S, F, w)
+    _check_local_solve(S, F, w, 1e-9)
+    b = S.point_sources(w.sources)
+    r = S.solve(b, w.tol, restart=w.restart, maxit=w.maxit)
+    assert r.converged.all() and r.rel_res.max() <= w.tol
+    _check_residual(S, F, w, b, r.x, w.tol)
+    S.close()
+    gc.collect()
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("cfg", [5, 3])
+def test_mixed_workload_against_fp64(cfg):
+    need_gpu()
+    from paper_2110_15113_amd import oras
+    w = wl.CONFIGS[cfg]()
+    say(f"full-size mixed config {cfg}")
+    F = op.make_fields(w.vel, w.Q, w.omega, w.h, w.npml)
+    S = _solver(w, oras.C64)
+    _check_local_solve(S, F, w, 1e-3)
+    b = S.point_sources(w.sources)
+    rm = S.solve(b, w.tol, restart=w.restart, maxit=w.maxit)
+    assert rm.converged.all() and rm.rel_res.max() <= w.tol
+    _check_residual(S, F, w, b, rm.x, w.tol)
+    xm = rm.x.clone()
+    S.close()
+    del S, rm
+    gc.collect()
+    torch.cuda.empty_cache()
+    S = _solver(w, oras.C128)
+    _check_coefficients(S, F, w)
+    b = S.point_sources(w.sources)
+    rt = S.solve(b, 1e-10, restart=w.restart, maxit=2000)
+    assert rt.converged.all()
+    _check_residual(S, F, w, b, rt.x, 1e-10)
+    err = (torch.linalg.vector_norm((xm - rt.x).reshape(-1))
+           / torch.linalg.vector_norm(rt.x.reshape(-1))).item()
+    say(f"config {cfg}: mixed(1e-6) vs fp64(1e-10) relative L2 = {err:.3e}")
+    assert err <= 1e-4, err
+    S.close()
+    gc.collect()
+    torch.cuda.empty_cache()
