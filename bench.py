@@ -201,7 +201,9 @@ def main():
         bytes_per = gb / gl
         peak = PEAK["fp32_mfma_TFLOPs"] if P == oras.C64 else PEAK["fp64_mfma_TFLOPs"]
         ach = flops_per / avg / 1e12
-        roof = {"kernel": "plane_gemm_kernel (MFMA 16x16x4, local substitutions)",
+        kname = ("plane_gemm_f32_kernel (MFMA 32x32x2 f32, local substitutions)" if P == oras.C64
+                 else "plane_gemm_f64_kernel (MFMA 16x16x4 f64, local substitutions)")
+        roof = {"kernel": kname,
                 "bound": "mfma", "achieved": round(ach, 2), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(ach / peak, 4), "traffic": traffic_for(w.name, bytes_per),
                 "algorithmic_bytes_per_launch": bytes_per, "algorithmic_flops_per_launch": flops_per,

@@ -11,20 +11,30 @@
 // independent, so no inter-work-group synchronisation is ever needed):
 //   * a right-hand-side kernel forms t for the plane of every subdomain
 //     (the restriction from the global vector is fused in);
-//   * a GEMM kernel with one wave per (subdomain, 32-row tile) streams its
-//     rows of S_k^{-1} from HBM and t from L2 into MFMA.  (Measured on
-//     gfx950 against variants staging t through LDS for 1-8 waves and
-//     against persistent balanced workers with register prefetch: this
-//     simplest form was the fastest.)
+//   * a GEMM kernel with one wave per (subdomain, 32-row tile, column group)
+//     streams its rows of S_k^{-1} from HBM and t through L2 into MFMA.
 // The GEMM epilogue stores the plane's rows and, once a plane is final,
 // writes the owned nodes to the output (restricted prolongation with a
 // Boolean partition of unity: each output entry is written once, no
 // atomics).
 //
 // Complex products on real MFMA: with A = Ar + i Ai and B = Br + i Bi, the
-// interleaved output columns (Re, Im) of C = A B come from two real
-// products per k-slice: Ar * [Br | Bi] + Ai * [-Bi | Br].  One 16x16x4
-// instruction covers 16 rows x 8 complex columns x 4 complex k.
+// interleaved output columns (Re, Im) of C = A B come from two real products
+// per k-slice, Ar * [Br | Bi] + Ai * [-Bi | Br].
+//
+// Complex FP32 (the mixed-precision path) uses the 32x32x2 instruction, which
+// on gfx950 sustains its full rate from a single wave with four independent
+// accumulators (the 16x16x4 form does not).  t is written by the
+// right-hand-side kernel directly in the operand order of that instruction,
+// so each wave fetches one 1 KB row of A and one 1 KB block of t per 4-deep
+// k-slice pair with no lane duplication; the second real operand [-Bi | Br]
+// is formed by swapping adjacent lanes (DPP).
+//
+// Complex FP64 uses the 16x16x4 FP64 instruction with t in row-major order.
+//
+// Work-groups are one wave.  The hardware hands consecutive work-group ids to
+// the 8 XCDs in turn, so the linear id is mapped such that all waves of one
+// subdomain land on the same XCD and share its L2 copy of t.
 #include <algorithm>
 
 #include "oras_internal.h"
@@ -33,130 +43,296 @@ namespace oras {
 
 namespace {
 
-__device__ inline long long tile_off(int I, int J, int nt) {
-  return ((long long)I * nt + J) * (TILE * TILE);
-}
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-// Both 16x16x4 instructions take A[row = lane % 16][k = lane / 16] and
-// B[k = lane / 16][col = lane % 16]; the result column is lane % 16, but the
-// result row of accumulator item t differs: 4 (lane / 16) + t for FP32,
-// lane / 16 + 4 t for FP64 (checked on gfx950).
-template <typename R> struct Mfma;
-template <> struct Mfma<float> {
-  typedef float acc_t __attribute__((ext_vector_type(4)));
-  static __device__ inline acc_t op(float a, float b, acc_t c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  static __device__ inline int out_row(int group, int t) { return 4 * group + t; }
-};
-template <> struct Mfma<double> {
-  typedef double acc_t __attribute__((ext_vector_type(4)));
-  static __device__ inline acc_t op(double a, double b, acc_t c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  static __device__ inline int out_row(int group, int t) { return group + 4 * t; }
-};
+constexpr int NXCD = 8;
 
 template <typename Z> struct Comp;
 template <> struct Comp<float2> { typedef float type; };
 template <> struct Comp<double2> { typedef double type; };
 
-// Plane right-hand sides of all subdomains: forward t = scale * v|_plane -
-// L_k y_{k-1}, backward t = U_k x_{k+1}; rows beyond the plane are zero.
+// Work-group id -> (subdomain, item) with all items of one subdomain on one XCD.
+__device__ inline void xcd_map(int items, int& sub, int& item) {
+  const int b = blockIdx.x, r = b / NXCD;
+  sub = (r / items) * NXCD + b % NXCD;
+  item = r % items;
+}
+
+__device__ inline bool plane_active(const SubDesc& sd, int k, int bwd) {
+  return bwd ? (k <= sd.sz - 2) : (k < sd.sz);
+}
+
+// Right-hand side of one plane row q, column c (q < p, c < s):
+// forward scale * v - L_k y_{k-1} (the L part only for k > 0), backward U_k x_{k+1}.
 template <typename R>
-__global__ void plane_rhs_kernel(const SubDesc* __restrict__ subs, int k, int bwd,
-                                 const C<R>* __restrict__ lca, const C<R>* __restrict__ ybuf,
-                                 C<R>* __restrict__ tvbuf, const double2* __restrict__ v,
-                                 const double* __restrict__ scale, int nx, int ny, int s) {
+__device__ inline C<R> plane_rhs_entry(const SubDesc& sd, int k, int bwd, int q, int c,
+                                       const C<R>* __restrict__ lca, const C<R>* __restrict__ ybuf,
+                                       const double2* __restrict__ v,
+                                       const double* __restrict__ scale, int nx, int ny, int s) {
   using T = C<R>;
-  const SubDesc sd = subs[blockIdx.y];
-  if (bwd ? (k > sd.sz - 2) : (k >= sd.sz)) return;
-  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long long)sd.P * s) return;
-  const int q = (int)(idx / s), c = (int)(idx % s);
   T t;
   t.x = 0;
   t.y = 0;
-  if (q < sd.p) {
-    const int qx = q % sd.sx, qy = q / sd.sx;
-    if (!bwd) {
-      const long long g = ((long long)(sd.lo[2] + k) * ny + sd.lo[1] + qy) * nx + sd.lo[0] + qx;
-      const double2 vv = v[g * s + c];
-      const double sc = scale ? scale[c] : 1.0;
-      t.x = (R)(vv.x * sc);
-      t.y = (R)(vv.y * sc);
-    }
-    if (bwd || k > 0) {
-      const long long nbox = (long long)sd.sx * sd.sy * sd.sz;
-      const long long node = ((long long)k * sd.sy + qy) * sd.sx + qx;
-      const T* L = lca + sd.lca_off;
-      const T* Yn = ybuf + (sd.y_off + (long long)(bwd ? k + 1 : k - 1) * sd.P) * s;
-      const int ez = bwd ? 1 : -1;
-      const R sg = bwd ? (R)1 : (R)-1;
-      for (int dy = -1; dy <= 1; ++dy) {
-        const int py = qy + dy;
-        if (py < 0 || py >= sd.sy) continue;
-        for (int dx = -1; dx <= 1; ++dx) {
-          const int px = qx + dx;
-          if (px < 0 || px >= sd.sx) continue;
-          const T l = L[eidx(dx, dy, ez) * nbox + node];
-          const T y = Yn[(long long)(py * sd.sx + px) * s + c];
-          t.x += sg * (l.x * y.x - l.y * y.y);
-          t.y += sg * (l.x * y.y + l.y * y.x);
-        }
+  const int qx = q % sd.sx, qy = q / sd.sx;
+  if (!bwd) {
+    const long long g = ((long long)(sd.lo[2] + k) * ny + sd.lo[1] + qy) * nx + sd.lo[0] + qx;
+    const double2 vv = v[g * s + c];
+    const double sc = scale ? scale[c] : 1.0;
+    t.x = (R)(vv.x * sc);
+    t.y = (R)(vv.y * sc);
+  }
+  if (bwd || k > 0) {
+    const long long nbox = (long long)sd.sx * sd.sy * sd.sz;
+    const long long node = ((long long)k * sd.sy + qy) * sd.sx + qx;
+    const T* L = lca + sd.lca_off;
+    const T* Yn = ybuf + (sd.y_off + (long long)(bwd ? k + 1 : k - 1) * sd.P) * s;
+    const int ez = bwd ? 1 : -1;
+    const R sg = bwd ? (R)1 : (R)-1;
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int py = qy + dy;
+      if (py < 0 || py >= sd.sy) continue;
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int px = qx + dx;
+        if (px < 0 || px >= sd.sx) continue;
+        const T l = L[eidx(dx, dy, ez) * nbox + node];
+        const T y = Yn[(long long)(py * sd.sx + px) * s + c];
+        t.x += sg * (l.x * y.x - l.y * y.y);
+        t.y += sg * (l.x * y.y + l.y * y.x);
       }
     }
   }
-  tvbuf[sd.tv_off * (long long)s + idx] = t;
+  return t;
 }
 
-// Y_k (=|-=) S_k^{-1} t for one 32-row tile of one subdomain: one wave,
-// S_k^{-1} rows streamed from HBM (one contiguous 8 KB tile per k-chunk),
-// t read through L1/L2 (it is shared by the subdomain's row tiles).  A
-// 16-row x 8-column x 4-k step is two MFMAs (real and imaginary part of A).
-template <typename R, typename Z, int NS>
-__global__ void __launch_bounds__(64)
-plane_gemm_kernel(const SubDesc* __restrict__ subs, int k, int bwd, const C<R>* __restrict__ fac,
-                   const C<R>* __restrict__ tvbuf, C<R>* __restrict__ ybuf, Z* __restrict__ z,
-                   int nx, int ny, int s, int c0) {
-  using T = C<R>;
-  using M = Mfma<R>;
-  using ZR = typename Comp<Z>::type;
+// ------------------------------------------------------- complex FP32 path --
+// t in operand order: per subdomain, per block cb of 16 columns, per group g
+// of 8 plane rows, per lane (h = lane / 32, rr = lane % 32) one float4 whose
+// component 2 p + e is part (rr & 1) of t[8 g + 4 p + 2 h + e][16 cb + rr / 2]
+// (zero beyond the plane or beyond column s).  One thread writes the real and
+// imaginary float4 of a lane pair: the four rows of (g, h) in column 16 cb + ci.
+__global__ void plane_rhs_f32_kernel(const SubDesc* __restrict__ subs, int k, int bwd,
+                                     const float2* __restrict__ lca,
+                                     const float2* __restrict__ ybuf, float4* __restrict__ tvm,
+                                     const double2* __restrict__ v,
+                                     const double* __restrict__ scale, int nx, int ny, int s,
+                                     int s16) {
   const SubDesc sd = subs[blockIdx.y];
-  if (bwd ? (k > sd.sz - 2) : (k >= sd.sz)) return;
-  const int I = blockIdx.x;
+  if (!plane_active(sd, k, bwd)) return;
+  const int G = sd.P / 8;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)(s16 / 16) * G * 32) return;
+  const int ci = (int)(idx % 16), h = (int)((idx / 16) % 2);
+  const int g = (int)((idx / 32) % G), cb = (int)(idx / (32LL * G));
+  const int c = cb * 16 + ci;
+  float re[4], im[4];
+#pragma unroll
+  for (int pe = 0; pe < 4; ++pe) {
+    const int q = 8 * g + 4 * (pe >> 1) + 2 * h + (pe & 1);
+    float2 t = make_float2(0.f, 0.f);
+    if (q < sd.p && c < s) t = plane_rhs_entry<float>(sd, k, bwd, q, c, lca, ybuf, v, scale, nx, ny, s);
+    re[pe] = t.x;
+    im[pe] = t.y;
+  }
+  float4* dst = tvm + sd.tv_off * s16 / 2 + ((long long)cb * G + g) * 64 + h * 32 + 2 * ci;
+  dst[0] = make_float4(re[0], re[1], re[2], re[3]);
+  dst[1] = make_float4(im[0], im[1], im[2], im[3]);
+}
+
+// Y_k (=|-=) S_k^{-1} t for one 32-row tile and NB blocks of 16 columns (one
+// wave).  A row of the factor tile layout holds, for each 4-k slice, rows
+// r = lane % 32 with entries 2 h, 2 h + 1 (h = lane / 32) in one float4; the
+// matching t operands come from the float4 of the operand-order layout.  The
+// next 32-k tile of both operands is prefetched into registers while the
+// current one feeds 16 NB instructions.
+template <typename Z, int NB>
+__global__ void __launch_bounds__(64)
+plane_gemm_f32_kernel(const SubDesc* __restrict__ subs, int nsub, int max_nt, int ncg, int cb0,
+                      int k, int bwd, const float2* __restrict__ fac,
+                      const float4* __restrict__ tvm, float2* __restrict__ ybuf,
+                      Z* __restrict__ z, int nx, int ny, int s, int s16) {
+  using ZR = typename Comp<Z>::type;
+  int sub, item;
+  xcd_map(max_nt * ncg, sub, item);
+  if (sub >= nsub) return;
+  const SubDesc sd = subs[sub];
+  if (!plane_active(sd, k, bwd)) return;
+  const int I = item / ncg, cg = item % ncg;
+  const int nt = sd.nt;
+  if (I >= nt) return;
+  const int P = sd.P, G = P / 8;
+  const int cbf = cb0 + cg * NB;   // first column block of this wave
+  const float4* A4 = reinterpret_cast<const float4*>(fac + sd.fac_off + (long long)k * P * P) +
+                     (long long)I * nt * 512;
+  const float4* B4 = tvm + sd.tv_off * s16 / 2 + (long long)cbf * G * 64;
+  const int lane = threadIdx.x, rr = lane & 31, h = lane >> 5;
+  const int aoff = rr * 2 + h;
+  const bool odd = (rr & 1) != 0;
+
+  f32x16 acc[NB][2];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      acc[b][0][j] = 0.f;
+      acc[b][1][j] = 0.f;
+    }
+  float4 sa[8], sb[4][NB];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) sa[q] = A4[q * 64 + aoff];
+#pragma unroll
+  for (int gg = 0; gg < 4; ++gg)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) sb[gg][b] = B4[((long long)b * G + gg) * 64 + lane];
+
+  for (int J = 0; J < nt; ++J) {
+    float4 ca[8], cbv[4][NB];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) ca[q] = sa[q];
+#pragma unroll
+    for (int gg = 0; gg < 4; ++gg)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) cbv[gg][b] = sb[gg][b];
+    if (J + 1 < nt) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) sa[q] = A4[(long long)(J + 1) * 512 + q * 64 + aoff];
+#pragma unroll
+      for (int gg = 0; gg < 4; ++gg)
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+          sb[gg][b] = B4[((long long)b * G + 4 * (J + 1) + gg) * 64 + lane];
+    }
+#pragma unroll
+    for (int gg = 0; gg < 4; ++gg)
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        const float4 a = ca[2 * gg + p];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const float ar = e ? a.z : a.x, ai = e ? a.w : a.y;
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            const float4 bv = cbv[gg][b];
+            const float b1 = p ? (e ? bv.w : bv.z) : (e ? bv.y : bv.x);
+            const float sw = __int_as_float(__builtin_amdgcn_update_dpp(
+                __float_as_int(b1), __float_as_int(b1), 0xB1, 0xF, 0xF, false));
+            const float b2 = odd ? sw : -sw;
+            acc[b][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, b1, acc[b][0], 0, 0, 0);
+            acc[b][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, b2, acc[b][1], 0, 0, 0);
+          }
+        }
+      }
+  }
+
+  // accumulator item i of lane l: row 8 (i / 4) + 4 (l / 32) + i % 4, real column l % 32
+  const bool final_plane = bwd || (k == sd.sz - 1);
+  float* Yk = reinterpret_cast<float*>(ybuf + (sd.y_off + (long long)k * P) * s);
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int row = I * TILE + 8 * (i / 4) + 4 * h + (i % 4);
+    float* yr = Yk + (long long)row * 2 * s;
+    long long zoff = -1;
+    if (final_plane && row < sd.p) {
+      const int qx = row % sd.sx, qy = row / sd.sx;
+      const int gx = sd.lo[0] + qx, gy = sd.lo[1] + qy, gz = sd.lo[2] + k;
+      if (gx >= sd.olo[0] && gx < sd.ohi[0] && gy >= sd.olo[1] && gy < sd.ohi[1] &&
+          gz >= sd.olo[2] && gz < sd.ohi[2])
+        zoff = (((long long)gz * ny + gy) * nx + gx) * s;
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int col = 16 * (cbf + b) + (rr >> 1);
+      if (col >= s) continue;
+      const int fi = 2 * col + (rr & 1);
+      float val = acc[b][0][i] + acc[b][1][i];
+      if (bwd) val = yr[fi] - val;
+      yr[fi] = val;
+      if (zoff >= 0) reinterpret_cast<ZR*>(z + zoff)[fi] = (ZR)val;
+    }
+  }
+}
+
+template <typename Z>
+void gemm_f32_dispatch(const OrasPlan& pl, int k, int bwd, const float2* fac, const float4* tvm,
+                       float2* ybuf, Z* z, int nx, int ny, int s, hipStream_t st) {
+  const int s16 = (int)pad16(s);
+  const int nblk = s16 / 16;
+  const int nsub8 = (pl.nsub + NXCD - 1) / NXCD * NXCD;
+  const int pairs = nblk / 2;
+  if (pairs > 0)
+    hipLaunchKernelGGL((plane_gemm_f32_kernel<Z, 2>), dim3((unsigned)(nsub8 * pl.max_nt * pairs)),
+                       dim3(64), 0, st, pl.subs, pl.nsub, pl.max_nt, pairs, 0, k, bwd, fac, tvm,
+                       ybuf, z, nx, ny, s, s16);
+  if (nblk % 2)
+    hipLaunchKernelGGL((plane_gemm_f32_kernel<Z, 1>), dim3((unsigned)(nsub8 * pl.max_nt)), dim3(64),
+                       0, st, pl.subs, pl.nsub, pl.max_nt, 1, nblk - 1, k, bwd, fac, tvm, ybuf, z,
+                       nx, ny, s, s16);
+}
+
+// ------------------------------------------------------- complex FP64 path --
+// Both 16x16x4 FP64 operands: A[row = lane % 16][k = lane / 16],
+// B[k = lane / 16][col = lane % 16]; result item t of lane l is row l / 16 + 4 t,
+// column l % 16 (checked on gfx950).
+__global__ void plane_rhs_f64_kernel(const SubDesc* __restrict__ subs, int k, int bwd,
+                                     const double2* __restrict__ lca,
+                                     const double2* __restrict__ ybuf, double2* __restrict__ tvbuf,
+                                     const double2* __restrict__ v,
+                                     const double* __restrict__ scale, int nx, int ny, int s) {
+  const SubDesc sd = subs[blockIdx.y];
+  if (!plane_active(sd, k, bwd)) return;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)sd.P * s) return;
+  const int q = (int)(idx / s), c = (int)(idx % s);
+  double2 t = make_double2(0.0, 0.0);
+  if (q < sd.p) t = plane_rhs_entry<double>(sd, k, bwd, q, c, lca, ybuf, v, scale, nx, ny, s);
+  tvbuf[sd.tv_off * (long long)pad16(s) + idx] = t;
+}
+
+// Y_k (=|-=) S_k^{-1} t for one 32-row tile and 8 NS columns (one wave); a
+// 16-row x 8-column x 4-k step is two instructions (real and imaginary A).
+template <int NS>
+__global__ void __launch_bounds__(64)
+plane_gemm_f64_kernel(const SubDesc* __restrict__ subs, int nsub, int max_nt, int k, int bwd,
+                      const double2* __restrict__ fac, const double2* __restrict__ tvbuf,
+                      double2* __restrict__ ybuf, double2* __restrict__ z, int nx, int ny, int s,
+                      int c0) {
+  int sub, I;
+  xcd_map(max_nt, sub, I);
+  if (sub >= nsub) return;
+  const SubDesc sd = subs[sub];
+  if (!plane_active(sd, k, bwd)) return;
   const int nt = sd.nt;
   if (I >= nt) return;
   const int P = sd.P;
-  const T* A = fac + sd.fac_off + (long long)k * P * P + tile_off(I, 0, nt);
-  const T* Bm = tvbuf + sd.tv_off * (long long)s + c0;
-  T* Yk = ybuf + (sd.y_off + (long long)k * P) * s;
+  const double2* A = fac + sd.fac_off + (long long)k * P * P + (long long)I * nt * (TILE * TILE);
+  const double2* Bm = tvbuf + sd.tv_off * pad16(s) + c0;
+  double2* Yk = ybuf + (sd.y_off + (long long)k * P) * s;
   const int lane = threadIdx.x;
   const int m = lane & 15, kk = lane >> 4;
   const int bn = m >> 1;
   const bool im = (m & 1) != 0;
-  typename M::acc_t acc[2][NS];
+  f64x4 acc[2][NS];
 #pragma unroll
   for (int rs = 0; rs < 2; ++rs)
 #pragma unroll
-    for (int ns = 0; ns < NS; ++ns) acc[rs][ns] = typename M::acc_t{0, 0, 0, 0};
+    for (int ns = 0; ns < NS; ++ns) acc[rs][ns] = f64x4{0, 0, 0, 0};
   for (int J = 0; J < nt; ++J) {
-    const T* tA = A + (long long)J * (TILE * TILE);
+    const double2* tA = A + (long long)J * (TILE * TILE);
 #pragma unroll 2
     for (int q = 0; q < 8; ++q) {
       const int kc = J * TILE + q * 4 + kk;
-      const T a0 = tA[(q * TILE + m) * 4 + kk];
-      const T a1 = tA[(q * TILE + 16 + m) * 4 + kk];
-      const T* brow = Bm + (long long)kc * s + bn;
+      const double2 a0 = tA[(q * TILE + m) * 4 + kk];
+      const double2 a1 = tA[(q * TILE + 16 + m) * 4 + kk];
+      const double2* brow = Bm + (long long)kc * s + bn;
 #pragma unroll
       for (int ns = 0; ns < NS; ++ns) {
-        const T bv = brow[ns * 8];
-        const R b1 = im ? bv.y : bv.x;
-        const R b2 = im ? bv.x : -bv.y;
-        acc[0][ns] = M::op(a0.x, b1, acc[0][ns]);
-        acc[0][ns] = M::op(a0.y, b2, acc[0][ns]);
-        acc[1][ns] = M::op(a1.x, b1, acc[1][ns]);
-        acc[1][ns] = M::op(a1.y, b2, acc[1][ns]);
+        const double2 bv = brow[ns * 8];
+        const double b1 = im ? bv.y : bv.x;
+        const double b2 = im ? bv.x : -bv.y;
+        acc[0][ns] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.x, b1, acc[0][ns], 0, 0, 0);
+        acc[0][ns] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.y, b2, acc[0][ns], 0, 0, 0);
+        acc[1][ns] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.x, b1, acc[1][ns], 0, 0, 0);
+        acc[1][ns] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.y, b2, acc[1][ns], 0, 0, 0);
       }
     }
   }
@@ -165,8 +341,8 @@ plane_gemm_kernel(const SubDesc* __restrict__ subs, int k, int bwd, const C<R>* 
   for (int rs = 0; rs < 2; ++rs)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int row = I * TILE + rs * 16 + M::out_row(kk, i);
-      R* yr = reinterpret_cast<R*>(Yk + (long long)row * s + c0);
+      const int row = I * TILE + rs * 16 + kk + 4 * i;
+      double* yr = reinterpret_cast<double*>(Yk + (long long)row * s + c0);
       long long zoff = -1;
       if (final_plane && row < sd.p) {
         const int qx = row % sd.sx, qy = row / sd.sx;
@@ -178,30 +354,25 @@ plane_gemm_kernel(const SubDesc* __restrict__ subs, int k, int bwd, const C<R>* 
 #pragma unroll
       for (int ns = 0; ns < NS; ++ns) {
         const int idx = ns * 16 + m;
-        R val = acc[rs][ns][i];
+        double val = acc[rs][ns][i];
         if (bwd) val = yr[idx] - val;
         yr[idx] = val;
-        if (zoff >= 0) reinterpret_cast<ZR*>(z + zoff)[idx] = (ZR)val;
+        if (zoff >= 0) reinterpret_cast<double*>(z + zoff)[idx] = val;
       }
     }
 }
 
-template <typename R, typename Z, int NS>
-void gemm_launch(const SubDesc* subs, int nsub, int max_nt, int k, int bwd, const C<R>* fac,
-                 const C<R>* tvbuf, C<R>* ybuf, Z* z, int nx, int ny, int s, int c0,
-                 hipStream_t st) {
-  hipLaunchKernelGGL((plane_gemm_kernel<R, Z, NS>), dim3(max_nt, nsub), dim3(64), 0, st, subs, k,
-                     bwd, fac, tvbuf, ybuf, z, nx, ny, s, c0);
-}
-
 // Columns in chunks of at most 64 right-hand sides (8 groups of 8).
-template <typename R, typename Z>
-void gemm_dispatch(const SubDesc* subs, int nsub, int max_nt, int k, int bwd, const C<R>* fac,
-                   const C<R>* tvbuf, C<R>* ybuf, Z* z, int nx, int ny, int s, hipStream_t st) {
+void gemm_f64_dispatch(const OrasPlan& pl, int k, int bwd, const double2* fac,
+                       const double2* tvbuf, double2* ybuf, double2* z, int nx, int ny, int s,
+                       hipStream_t st) {
+  const int nsub8 = (pl.nsub + NXCD - 1) / NXCD * NXCD;
+  const dim3 grid((unsigned)(nsub8 * pl.max_nt));
   for (int c0 = 0; c0 < s; c0 += 8 * RHS_ALIGN) {
     const int groups = std::min(8, (s - c0) / RHS_ALIGN);
-#define ORAS_GEMM(NS_) \
-  gemm_launch<R, Z, NS_>(subs, nsub, max_nt, k, bwd, fac, tvbuf, ybuf, z, nx, ny, s, c0, st)
+#define ORAS_GEMM(NS_)                                                                           \
+  hipLaunchKernelGGL((plane_gemm_f64_kernel<NS_>), grid, dim3(64), 0, st, pl.subs, pl.nsub,     \
+                     pl.max_nt, k, bwd, fac, tvbuf, ybuf, z, nx, ny, s, c0)
     switch (groups) {
       case 1: ORAS_GEMM(1); break;
       case 2: ORAS_GEMM(2); break;
@@ -216,24 +387,62 @@ void gemm_dispatch(const SubDesc* subs, int nsub, int max_nt, int k, int bwd, co
   }
 }
 
+template <typename Z>
+void plane_step_f32(const OrasPlan& pl, int k, int bwd, const float2* fac, const float2* lca,
+                    float2* ybuf, float2* tvbuf, const double2* v, const double* scale, Z* z,
+                    int nx, int ny, int s, hipStream_t st, hipEvent_t* ev) {
+  const int s16 = (int)pad16(s);
+  const long long nthr = (long long)(s16 / 16) * (pl.max_p / 8) * 32;
+  const int bs = 256;
+  hipLaunchKernelGGL(plane_rhs_f32_kernel, dim3((unsigned)((nthr + bs - 1) / bs), (unsigned)pl.nsub),
+                     dim3(bs), 0, st, pl.subs, k, bwd, lca, ybuf,
+                     reinterpret_cast<float4*>(tvbuf), v, scale, nx, ny, s, s16);
+  if (ev) (void)hipEventRecord(ev[0], st);
+  gemm_f32_dispatch<Z>(pl, k, bwd, fac, reinterpret_cast<const float4*>(tvbuf), ybuf, z, nx, ny,
+                       s, st);
+  if (ev) (void)hipEventRecord(ev[1], st);
+}
+
+void plane_step_f64(const OrasPlan& pl, int k, int bwd, const double2* fac, const double2* lca,
+                    double2* ybuf, double2* tvbuf, const double2* v, const double* scale,
+                    double2* z, int nx, int ny, int s, hipStream_t st, hipEvent_t* ev) {
+  const int bs = 256;
+  const dim3 grhs((unsigned)((pl.max_p * s + bs - 1) / bs), (unsigned)pl.nsub);
+  hipLaunchKernelGGL(plane_rhs_f64_kernel, grhs, dim3(bs), 0, st, pl.subs, k, bwd, lca, ybuf,
+                     tvbuf, v, scale, nx, ny, s);
+  if (ev) (void)hipEventRecord(ev[0], st);
+  gemm_f64_dispatch(pl, k, bwd, fac, tvbuf, ybuf, z, nx, ny, s, st);
+  if (ev) (void)hipEventRecord(ev[1], st);
+}
+
+template <typename R, typename Z> struct Stepper;
+template <typename Z> struct Stepper<float, Z> {
+  static void run(const OrasPlan& pl, int k, int bwd, const float2* fac, const float2* lca,
+                  float2* ybuf, float2* tvbuf, const double2* v, const double* scale, Z* z, int nx,
+                  int ny, int s, hipStream_t st, hipEvent_t* ev) {
+    plane_step_f32<Z>(pl, k, bwd, fac, lca, ybuf, tvbuf, v, scale, z, nx, ny, s, st, ev);
+  }
+};
+template <> struct Stepper<double, double2> {
+  static void run(const OrasPlan& pl, int k, int bwd, const double2* fac, const double2* lca,
+                  double2* ybuf, double2* tvbuf, const double2* v, const double* scale,
+                  double2* z, int nx, int ny, int s, hipStream_t st, hipEvent_t* ev) {
+    plane_step_f64(pl, k, bwd, fac, lca, ybuf, tvbuf, v, scale, z, nx, ny, s, st, ev);
+  }
+};
+
 }  // namespace
 
 template <typename R, typename Z>
 void launch_oras_apply(const OrasPlan& plan, const C<R>* fac, const C<R>* lca, C<R>* ybuf,
                        C<R>* tvbuf, const double2* v, const double* scale, Z* z, int nx, int ny,
                        int s, hipStream_t st, hipEvent_t* gemm_ev) {
-  const int bs = 256;
-  const dim3 grhs((unsigned)((plan.max_p * s + bs - 1) / bs), (unsigned)plan.nsub);
   const int nsteps = 2 * plan.max_sz - 1;
   for (int step = 0; step < nsteps; ++step) {
     const bool bwd = step >= plan.max_sz;
     const int k = bwd ? 2 * plan.max_sz - 2 - step : step;
-    hipLaunchKernelGGL((plane_rhs_kernel<R>), grhs, dim3(bs), 0, st, plan.subs, k, bwd ? 1 : 0, lca,
-                       ybuf, tvbuf, v, scale, nx, ny, s);
-    if (gemm_ev) (void)hipEventRecord(gemm_ev[2 * step], st);
-    gemm_dispatch<R, Z>(plan.subs, plan.nsub, plan.max_nt, k, bwd ? 1 : 0, fac, tvbuf, ybuf, z,
-                        nx, ny, s, st);
-    if (gemm_ev) (void)hipEventRecord(gemm_ev[2 * step + 1], st);
+    Stepper<R, Z>::run(plan, k, bwd ? 1 : 0, fac, lca, ybuf, tvbuf, v, scale, z, nx, ny, s, st,
+                       gemm_ev ? gemm_ev + 2 * step : nullptr);
   }
 }
 

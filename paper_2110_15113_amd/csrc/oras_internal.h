@@ -46,6 +46,8 @@ template <typename To, typename From> __host__ __device__ inline To ccast(From a
 // ---------------------------------------------------------------- layouts --
 constexpr int TILE = 32;        // factor tile edge (complex entries)
 constexpr int RHS_ALIGN = 8;    // internal right-hand-side count granularity
+// Column count of the plane right-hand-side buffer (blocks of 16 columns).
+__host__ __device__ constexpr inline long long pad16(long long s) { return (s + 15) / 16 * 16; }
 
 // Neighbour offset (ex, ey, ez) in {-1,0,1}^3 -> coefficient slot.
 __host__ __device__ constexpr inline int eidx(int ex, int ey, int ez) {
@@ -75,7 +77,7 @@ struct SubDesc {
   long long lca_off;     // offset of the local coefficient array (27 * sx*sy*sz)
   long long y_off;       // offset of the local solution buffer (sz * P * s)  [in units of P*s]
   long long t_off;       // offset of the scratch plane (P*P) used while factoring
-  long long tv_off;      // offset of the plane right-hand side (P * s)
+  long long tv_off;      // offset of the plane right-hand side (P rows of pad16(s) columns)
 };
 
 // ------------------------------------------------------------- launchers --

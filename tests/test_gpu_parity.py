@@ -49,6 +49,11 @@ ORAS_CASES = [
     dict(n=(19, 17, 15), parts=(2, 3, 2), ov=1, npml=2, q=50.0, nrhs=3),
     dict(n=(26, 14, 12), parts=(3, 1, 2), ov=3, npml=2, q=None, nrhs=9),
     dict(n=(12, 12, 12), parts=(1, 1, 1), ov=2, npml=2, q=70.0, nrhs=1),
+    # column blocks of the FP32 plane GEMM: a pair with masked columns, a pair
+    # plus a single block, two pairs
+    dict(n=(18, 16, 14), parts=(2, 2, 1), ov=2, npml=2, q=60.0, nrhs=20),
+    dict(n=(15, 19, 13), parts=(1, 2, 2), ov=1, npml=2, q=None, nrhs=37),
+    dict(n=(14, 14, 14), parts=(2, 2, 2), ov=2, npml=2, q=80.0, nrhs=64),
 ]
 
 
