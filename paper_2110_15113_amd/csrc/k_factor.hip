@@ -21,6 +21,8 @@
 // 32 x 32 pivot blocks (no pivoting; a zero or non-finite pivot is reported):
 //     A_kk <- A_kk^{-1};  A_kJ <- A_kk^{-1} A_kJ;  A_IJ <- A_IJ - A_Ik A_kJ;
 //     A_Ik <- -A_Ik A_kk^{-1}.
+// The trailing update A_IJ -= A_Ik A_kJ, which carries almost all the work,
+// runs on MFMA; the panel and pivot-block steps are small and use VALU.
 #include "oras_internal.h"
 
 namespace oras {
@@ -248,31 +250,164 @@ __global__ void __launch_bounds__(64) gj_rowpanel_kernel(const SubDesc* subs, in
     for (int j = 0; j < 4; ++j) dst[o + i * 4 + j] = out[i][j];
 }
 
-// A_IJ <- A_IJ - A_Ik A_kJ   (I, J != kb)
-template <typename R>
-__global__ void __launch_bounds__(64) gj_update_kernel(const SubDesc* subs, int k, int kb,
-                                                       C<R>* fac) {
-  using T = C<R>;
-  __shared__ T X[TILE][TILE + 1];
-  __shared__ T Y[TILE][TILE + 1];
-  const SubDesc sd = subs[blockIdx.z];
-  const int I = blockIdx.y, J = blockIdx.x;
-  if (k >= sd.sz || kb >= sd.nt || I >= sd.nt || J >= sd.nt || I == kb || J == kb) return;
-  T* base = fac + sd.fac_off + (long long)k * sd.P * sd.P;
-  load_tile_lds(base + tile_off(I, kb, sd.nt), X);
-  load_tile_lds(base + tile_off(kb, J, sd.nt), Y);
-  __syncthreads();
-  T out[4][4];
-  tile_product(X, Y, out);
-  T* dst = base + tile_off(I, J, sd.nt);
-  const int o = block_base();
-  for (int i = 0; i < 4; ++i)
-    for (int j = 0; j < 4; ++j) {
-      T v = dst[o + i * 4 + j];
-      v.x -= out[i][j].x;
-      v.y -= out[i][j].y;
-      dst[o + i * 4 + j] = v;
+// A_IJ <- A_IJ - A_Ik A_kJ   (I, J != kb) on MFMA, one wave per 32 x 32 tile.
+// Work-group ids are mapped so that all tiles of one subdomain run on the same
+// XCD and read the pivot row and column panels from its L2.
+constexpr int NXCD = 8;
+__device__ inline void tile_map(int items, int& sub, int& item) {
+  const int b = blockIdx.x, r = b / NXCD;
+  sub = (r / items) * NXCD + b % NXCD;
+  item = r % items;
+}
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename R> struct GjUpdate;
+
+// Complex FP32 on the 32x32x2 instruction.  The three tiles are fetched
+// together up front (A_Ik and A_kJ into LDS, A_IJ into registers), so a wave
+// waits for memory once.  A_Ik rows come from the tile layout (lane l: row
+// l % 32, entries 2 (l / 32), 2 (l / 32) + 1 of each 4-column run); B = A_kJ
+// is read per lane as the complex entry (k, col) and split into [Br | Bi] and
+// [-Bi | Br] by lane parity.  Real and imaginary A parts accumulate
+// separately (four independent chains).
+template <> struct GjUpdate<float> {
+  static __device__ void run(float2* __restrict__ C, const float2* __restrict__ X,
+                             const float2* __restrict__ Y) {
+    __shared__ float4 sX[512], sY[512];
+    const int lane = threadIdx.x, rr = lane & 31, h = lane >> 5;
+    const bool odd = (rr & 1) != 0;
+    float* Cf = reinterpret_cast<float*>(C);
+    float4 xr[8], yr[8];
+    float cv[2][16];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      xr[i] = reinterpret_cast<const float4*>(X)[i * 64 + lane];
+      yr[i] = reinterpret_cast<const float4*>(Y)[i * 64 + lane];
     }
+    // accumulator item i of lane l: row 8 (i / 4) + 4 (l / 32) + i % 4, real column l % 32
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int row = 8 * (i / 4) + 4 * h + (i % 4);
+#pragma unroll
+      for (int b = 0; b < 2; ++b) cv[b][i] = Cf[2 * in_tile(row, 16 * b + (rr >> 1)) + (rr & 1)];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      sX[i * 64 + lane] = xr[i];
+      sY[i * 64 + lane] = yr[i];
+    }
+    __syncthreads();
+    const float2* Ys = reinterpret_cast<const float2*>(sY);
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        acc[b][0][j] = 0.f;
+        acc[b][1][j] = 0.f;
+      }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const float4 a = sX[q * 64 + rr * 2 + h];
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const float ar = e ? a.z : a.x, ai = e ? a.w : a.y;
+        const int kr = 4 * q + 2 * h + e;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const float2 v = Ys[in_tile(kr, 16 * b + (rr >> 1))];
+          const float b1 = odd ? v.y : v.x, b2 = odd ? v.x : -v.y;
+          acc[b][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, b1, acc[b][0], 0, 0, 0);
+          acc[b][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, b2, acc[b][1], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int row = 8 * (i / 4) + 4 * h + (i % 4);
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        Cf[2 * in_tile(row, 16 * b + (rr >> 1)) + (rr & 1)] = cv[b][i] - (acc[b][0][i] + acc[b][1][i]);
+    }
+  }
+};
+
+// Complex FP64 on the 16x16x4 FP64 instruction (operands A[row = l % 16][k =
+// l / 16], B[k = l / 16][col = l % 16]; result item t of lane l is row
+// l / 16 + 4 t): two 16-row halves x four 8-column groups, tiles fetched up
+// front as in the FP32 form.
+template <> struct GjUpdate<double> {
+  static __device__ void run(double2* __restrict__ C, const double2* __restrict__ X,
+                             const double2* __restrict__ Y) {
+    __shared__ double2 sX[1024], sY[1024];
+    const int lane = threadIdx.x, m = lane & 15, kk = lane >> 4;
+    const bool odd = (m & 1) != 0;
+    double* Cd = reinterpret_cast<double*>(C);
+    double2 xr[16], yr[16];
+    double cv[2][4][4];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      xr[i] = X[i * 64 + lane];
+      yr[i] = Y[i * 64 + lane];
+    }
+#pragma unroll
+    for (int rs = 0; rs < 2; ++rs)
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int ns = 0; ns < 4; ++ns)
+          cv[rs][t][ns] = Cd[2 * in_tile(rs * 16 + kk + 4 * t, 8 * ns + (m >> 1)) + (m & 1)];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      sX[i * 64 + lane] = xr[i];
+      sY[i * 64 + lane] = yr[i];
+    }
+    __syncthreads();
+    f64x4 acc[2][4];
+#pragma unroll
+    for (int rs = 0; rs < 2; ++rs)
+#pragma unroll
+      for (int ns = 0; ns < 4; ++ns) acc[rs][ns] = f64x4{0, 0, 0, 0};
+#pragma unroll 2
+    for (int q = 0; q < 8; ++q) {
+      const double2 a0 = sX[(q * TILE + m) * 4 + kk];
+      const double2 a1 = sX[(q * TILE + 16 + m) * 4 + kk];
+      const int kr = 4 * q + kk;
+#pragma unroll
+      for (int ns = 0; ns < 4; ++ns) {
+        const double2 v = sY[in_tile(kr, 8 * ns + (m >> 1))];
+        const double b1 = odd ? v.y : v.x, b2 = odd ? v.x : -v.y;
+        acc[0][ns] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.x, b1, acc[0][ns], 0, 0, 0);
+        acc[0][ns] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.y, b2, acc[0][ns], 0, 0, 0);
+        acc[1][ns] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.x, b1, acc[1][ns], 0, 0, 0);
+        acc[1][ns] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.y, b2, acc[1][ns], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int rs = 0; rs < 2; ++rs)
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int ns = 0; ns < 4; ++ns)
+          Cd[2 * in_tile(rs * 16 + kk + 4 * t, 8 * ns + (m >> 1)) + (m & 1)] =
+              cv[rs][t][ns] - acc[rs][ns][t];
+  }
+};
+
+template <typename R>
+__global__ void __launch_bounds__(64) gj_update_kernel(const SubDesc* subs, int nsub, int max_nt,
+                                                       int k, int kb, C<R>* fac) {
+  int sub, item;
+  tile_map(max_nt * max_nt, sub, item);
+  if (sub >= nsub) return;
+  const SubDesc sd = subs[sub];
+  const int I = item / max_nt, J = item % max_nt;
+  if (k >= sd.sz || kb >= sd.nt || I >= sd.nt || J >= sd.nt || I == kb || J == kb) return;
+  C<R>* base = fac + sd.fac_off + (long long)k * sd.P * sd.P;
+  GjUpdate<R>::run(base + tile_off(I, J, sd.nt), base + tile_off(I, kb, sd.nt),
+                   base + tile_off(kb, J, sd.nt));
 }
 
 // A_Ik <- -A_Ik A_kk^{-1}   (I != kb)
@@ -308,6 +443,7 @@ template <typename R>
 void launch_factor_plane(const SubDesc* subs_dev, int nsub, int k, int max_nt, C<R>* fac,
                          C<R>* tbuf, const C<R>* lca, int* status, hipStream_t st) {
   const dim3 g2(max_nt, max_nt, nsub);
+  const int nsub8 = (nsub + NXCD - 1) / NXCD * NXCD;
   if (k > 0)
     hipLaunchKernelGGL((schur_T_kernel<R>), g2, dim3(256), 0, st, subs_dev, k, fac, tbuf, lca);
   hipLaunchKernelGGL((build_S_kernel<R>), g2, dim3(256), 0, st, subs_dev, k, fac, tbuf, lca);
@@ -316,7 +452,8 @@ void launch_factor_plane(const SubDesc* subs_dev, int nsub, int k, int max_nt, C
                        status);
     hipLaunchKernelGGL((gj_rowpanel_kernel<R>), dim3(max_nt, nsub), dim3(64), 0, st, subs_dev, k,
                        kb, fac);
-    hipLaunchKernelGGL((gj_update_kernel<R>), g2, dim3(64), 0, st, subs_dev, k, kb, fac);
+    hipLaunchKernelGGL((gj_update_kernel<R>), dim3((unsigned)(nsub8 * max_nt * max_nt)), dim3(64),
+                       0, st, subs_dev, nsub, max_nt, k, kb, fac);
     hipLaunchKernelGGL((gj_colpanel_kernel<R>), dim3(max_nt, nsub), dim3(64), 0, st, subs_dev, k,
                        kb, fac);
   }
