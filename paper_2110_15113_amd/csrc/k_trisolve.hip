@@ -112,34 +112,89 @@ __device__ inline C<R> plane_rhs_entry(const SubDesc& sd, int k, int bwd, int q,
 // t in operand order: per subdomain, per block cb of 16 columns, per group g
 // of 8 plane rows, per lane (h = lane / 32, rr = lane % 32) one float4 whose
 // component 2 p + e is part (rr & 1) of t[8 g + 4 p + 2 h + e][16 cb + rr / 2]
-// (zero beyond the plane or beyond column s).  One thread writes the real and
-// imaginary float4 of a lane pair: the four rows of (g, h) in column 16 cb + ci.
-__global__ void plane_rhs_f32_kernel(const SubDesc* __restrict__ subs, int k, int bwd,
-                                     const float2* __restrict__ lca,
-                                     const float2* __restrict__ ybuf, float4* __restrict__ tvm,
-                                     const double2* __restrict__ v,
-                                     const double* __restrict__ scale, int nx, int ny, int s,
-                                     int s16) {
-  const SubDesc sd = subs[blockIdx.y];
+// (zero beyond the plane or beyond column s).
+//
+// A work-group forms t for 16 plane rows (two groups of 8) and 32 columns (two
+// column blocks).  Sixteen lanes share a row, two columns each, so every
+// vector load of y or v covers whole cache lines of one row and a coupling
+// coefficient is one broadcast per row; the tile is transposed through LDS and
+// written out as whole float4 operands, one per thread.
+constexpr int RB_ROWS = 16;
+constexpr int RB_THREADS = RB_ROWS * 16;
+
+__global__ void __launch_bounds__(RB_THREADS)
+plane_rhs_f32_kernel(const SubDesc* __restrict__ subs, int nsub, int nrb, int ncc, int k, int bwd,
+                     const float2* __restrict__ lca, const float2* __restrict__ ybuf,
+                     float4* __restrict__ tvm, const double2* __restrict__ v,
+                     const double* __restrict__ scale, int nx, int ny, int s, int s16) {
+  __shared__ float2 tile[RB_ROWS][33];
+  int sub, item;
+  xcd_map(nrb * ncc, sub, item);
+  if (sub >= nsub) return;
+  const SubDesc sd = subs[sub];
   if (!plane_active(sd, k, bwd)) return;
   const int G = sd.P / 8;
-  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long long)(s16 / 16) * G * 32) return;
-  const int ci = (int)(idx % 16), h = (int)((idx / 16) % 2);
-  const int g = (int)((idx / 32) % G), cb = (int)(idx / (32LL * G));
-  const int c = cb * 16 + ci;
-  float re[4], im[4];
+  const int cc = item / nrb, g0 = 2 * (item % nrb);
+  if (g0 >= G) return;
+
+  const int tid = threadIdx.x;
+  const int rl = tid >> 4, cp = tid & 15;
+  const int q = 8 * g0 + rl;
+  const int c = 32 * cc + 2 * cp;
+  float2 t0 = make_float2(0.f, 0.f), t1 = make_float2(0.f, 0.f);
+  if (q < sd.p && c < s) {
+    const int qx = q % sd.sx, qy = q / sd.sx;
+    if (!bwd) {
+      const long long gn = ((long long)(sd.lo[2] + k) * ny + sd.lo[1] + qy) * nx + sd.lo[0] + qx;
+      const double2 v0 = v[gn * s + c], v1 = v[gn * s + c + 1];
+      const double s0 = scale ? scale[c] : 1.0, s1 = scale ? scale[c + 1] : 1.0;
+      t0 = make_float2((float)(v0.x * s0), (float)(v0.y * s0));
+      t1 = make_float2((float)(v1.x * s1), (float)(v1.y * s1));
+    }
+    if (bwd || k > 0) {
+      const long long nbox = (long long)sd.sx * sd.sy * sd.sz;
+      const long long node = ((long long)k * sd.sy + qy) * sd.sx + qx;
+      const float2* L = lca + sd.lca_off;
+      const float2* Yn = ybuf + (sd.y_off + (long long)(bwd ? k + 1 : k - 1) * sd.P) * s + c;
+      const int ez = bwd ? 1 : -1;
+      const float sg = bwd ? 1.f : -1.f;
+      // couplings that leave the box are stored as exact zeros in the local
+      // coefficients (the restricted rows drop them), so clamped neighbour
+      // indices contribute nothing and the loads need no branches
 #pragma unroll
-  for (int pe = 0; pe < 4; ++pe) {
-    const int q = 8 * g + 4 * (pe >> 1) + 2 * h + (pe & 1);
-    float2 t = make_float2(0.f, 0.f);
-    if (q < sd.p && c < s) t = plane_rhs_entry<float>(sd, k, bwd, q, c, lca, ybuf, v, scale, nx, ny, s);
-    re[pe] = t.x;
-    im[pe] = t.y;
+      for (int dy = -1; dy <= 1; ++dy) {
+        const int py = min(max(qy + dy, 0), sd.sy - 1);
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int px = min(max(qx + dx, 0), sd.sx - 1);
+          float2 l = L[eidx(dx, dy, ez) * nbox + node];
+          l.x *= sg;
+          l.y *= sg;
+          const float4 y2 = *reinterpret_cast<const float4*>(Yn + (long long)(py * sd.sx + px) * s);
+          t0.x += l.x * y2.x - l.y * y2.y;
+          t0.y += l.x * y2.y + l.y * y2.x;
+          t1.x += l.x * y2.z - l.y * y2.w;
+          t1.y += l.x * y2.w + l.y * y2.z;
+        }
+      }
+    }
   }
-  float4* dst = tvm + sd.tv_off * s16 / 2 + ((long long)cb * G + g) * 64 + h * 32 + 2 * ci;
-  dst[0] = make_float4(re[0], re[1], re[2], re[3]);
-  dst[1] = make_float4(im[0], im[1], im[2], im[3]);
+  tile[rl][2 * cp] = t0;
+  tile[rl][2 * cp + 1] = t1;
+  __syncthreads();
+  // one float4 per thread: column block 2 cc + cbl, row group g0 + gl, lane
+  const int cbl = tid >> 7, gl = (tid >> 6) & 1, lane = tid & 63;
+  const int cb = 2 * cc + cbl;
+  if (cb >= s16 / 16 || g0 + gl >= G) return;
+  const int h = lane >> 5, rr = lane & 31, ci = 16 * cbl + (rr >> 1);
+  float val[4];
+#pragma unroll
+  for (int j4 = 0; j4 < 4; ++j4) {
+    const float2 w = tile[8 * gl + 4 * (j4 >> 1) + 2 * h + (j4 & 1)][ci];
+    val[j4] = (rr & 1) ? w.y : w.x;
+  }
+  tvm[sd.tv_off * s16 / 2 + ((long long)cb * G + g0 + gl) * 64 + lane] =
+      make_float4(val[0], val[1], val[2], val[3]);
 }
 
 // Y_k (=|-=) S_k^{-1} t for one 32-row tile and NB blocks of 16 columns (one
@@ -395,10 +450,11 @@ void plane_step_f32(const OrasPlan& pl, int k, int bwd, const float2* fac, const
                     float2* ybuf, float2* tvbuf, const double2* v, const double* scale, Z* z,
                     int nx, int ny, int s, hipStream_t st, hipEvent_t* ev) {
   const int s16 = (int)pad16(s);
-  const long long nthr = (long long)(s16 / 16) * (pl.max_p / 8) * 32;
-  const int bs = 256;
-  hipLaunchKernelGGL(plane_rhs_f32_kernel, dim3((unsigned)((nthr + bs - 1) / bs), (unsigned)pl.nsub),
-                     dim3(bs), 0, st, pl.subs, k, bwd, lca, ybuf,
+  const int nrb = (int)((pl.max_p + RB_ROWS - 1) / RB_ROWS);   // 16-row blocks
+  const int ncc = (s16 + 31) / 32;                               // 32-column chunks
+  const int nsub8 = (pl.nsub + NXCD - 1) / NXCD * NXCD;
+  hipLaunchKernelGGL(plane_rhs_f32_kernel, dim3((unsigned)(nsub8 * nrb * ncc)), dim3(RB_THREADS), 0,
+                     st, pl.subs, pl.nsub, nrb, ncc, k, bwd, lca, ybuf,
                      reinterpret_cast<float4*>(tvbuf), v, scale, nx, ny, s, s16);
   if (ev) (void)hipEventRecord(ev[0], st);
   gemm_f32_dispatch<Z>(pl, k, bwd, fac, reinterpret_cast<const float4*>(tvbuf), ybuf, z, nx, ny,
