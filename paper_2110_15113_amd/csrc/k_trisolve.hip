@@ -59,8 +59,12 @@ __device__ inline void xcd_map(int items, int& sub, int& item) {
   item = r % items;
 }
 
+// A plane step does work for a subdomain on every forward plane, and on the
+// backward planes from sz - 2 down to its lowest owned plane: only owned nodes
+// are written out and the backward recursion runs downward, so the planes
+// below the owned range feed nothing.
 __device__ inline bool plane_active(const SubDesc& sd, int k, int bwd) {
-  return bwd ? (k <= sd.sz - 2) : (k < sd.sz);
+  return bwd ? (k <= sd.sz - 2 && k >= sd.olo[2] - sd.lo[2]) : (k < sd.sz);
 }
 
 // Right-hand side of one plane row q, column c (q < p, c < s):

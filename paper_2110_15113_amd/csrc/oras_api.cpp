@@ -585,7 +585,7 @@ oras_status oras_factor_subdomains(oras_ctx c, const int parts[3], int overlap, 
     for (int k = 0; k < d.sz; ++k) {
       c->plane_p2_fwd[k] += (double)d.p * d.p;
       c->plane_p_fwd[k] += d.p;
-      if (k <= d.sz - 2) {
+      if (k <= d.sz - 2 && k >= d.olo[2] - d.lo[2]) {   // backward planes that feed the output
         c->plane_p2_bwd[k] += (double)d.p * d.p;
         c->plane_p_bwd[k] += d.p;
       }
