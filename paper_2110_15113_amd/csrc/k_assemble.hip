@@ -19,6 +19,8 @@
 // mean family weight of the support nodes, K_a = S / s_a^2 the PML metric at
 // the point and f = 1/2 for the in-plane family (each axis lies in two
 // planes), 1 otherwise.
+#include <algorithm>
+
 #include "oras_internal.h"
 
 namespace oras {
@@ -260,10 +262,28 @@ __global__ void pml_kernel(double2* prof, int n, int npml, double h, double omeg
   prof[t] = make_double2(1.0, sigma / omega);
 }
 
-__global__ void max_reduce_kernel(const double* x, long long n, double* out) {
+// Maximum of x in two fixed-order stages: MAXRED_BLOCKS partial maxima, then one
+// work-group over them (out[0]; out[1 ..] holds the partials).
+constexpr int MAXRED_BLOCKS = 1024;
+__global__ void max_partial_kernel(const double* x, long long n, double* part) {
   __shared__ double red[256];
   double m = -INFINITY;
-  for (long long i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, x[i]);
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    m = fmax(m, x[i]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void max_reduce_kernel(const double* part, int np, double* out) {
+  __shared__ double red[256];
+  double m = -INFINITY;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) m = fmax(m, part[i]);
   red[threadIdx.x] = m;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
@@ -311,8 +331,11 @@ void launch_pml(double2* prof, int n, int npml, double h, double omega, double c
                      h, omega, c_ref, R0, power, low, high);
 }
 
+// out must hold 1 + MAXRED_BLOCKS doubles.
 void launch_max_reduce(const double* x, long long n, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(max_reduce_kernel, dim3(1), dim3(256), 0, s, x, n, out);
+  const int nb = (int)std::min<long long>(MAXRED_BLOCKS, std::max<long long>(1, (n + 255) / 256));
+  hipLaunchKernelGGL(max_partial_kernel, dim3(nb), dim3(256), 0, s, x, n, out + 1);
+  hipLaunchKernelGGL(max_reduce_kernel, dim3(1), dim3(256), 0, s, out + 1, nb, out);
 }
 
 }  // namespace oras

@@ -425,7 +425,7 @@ oras_status oras_assemble(oras_ctx c, const oras_grid* g, const double* vel_dev,
   TRY(dev_alloc(c, c->coef128, (size_t)n * 27 * sizeof(double2)));
   if (stencil_prec == ORAS_C64) TRY(dev_alloc(c, c->coef64, (size_t)n * 27 * sizeof(float2)));
   TRY(dev_alloc(c, c->wtab, t.w.size() * sizeof(double)));
-  TRY(dev_alloc(c, c->scratch8, 64));
+  TRY(dev_alloc(c, c->scratch8, (1 + 1024) * sizeof(double)));   // max + partial maxima
   HIP_TRY(c, hipMemcpyAsync(c->wtab.p, t.w.data(), t.w.size() * sizeof(double),
                             hipMemcpyHostToDevice, c->stream));
   // velocity checks and the PML reference velocity (maximum of the model)

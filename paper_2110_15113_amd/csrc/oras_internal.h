@@ -91,6 +91,7 @@ void launch_fields(const double* vel, const double* q, const double* m_override,
                    int keep_weights);
 void launch_pml(double2* prof, int n, int npml, double h, double omega, double c_ref, double R0,
                 int power, int low, int high, hipStream_t s);
+// out[0] = max(x); out must hold 1 + 1024 doubles (partial maxima after the first)
 void launch_max_reduce(const double* x, long long n, double* out, hipStream_t s);
 
 // Stencil: y = A x (or y = b - A x when b != null).  x precision Tx, coefficient
