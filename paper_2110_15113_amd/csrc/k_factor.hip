@@ -121,8 +121,7 @@ __global__ void __launch_bounds__(256) build_S_kernel(const SubDesc* subs, int k
             if (qx < 0 || qx >= sd.sx) continue;
             const T l = L[eidx(ex, ey, -1) * nbox + node];
             const T t = Tm[mat_off(qy * sd.sx + qx, c, nt)];
-            v.x -= l.x * t.x - l.y * t.y;
-            v.y -= l.x * t.y + l.y * t.x;
+            cfms(v, l, t);
           }
         }
       }
@@ -201,8 +200,7 @@ __global__ void __launch_bounds__(256) gj_diag_kernel(const SubDesc* subs, int k
         const T f = A[r][piv];
         const T g = A[piv][c];
         T v = A[r][c];
-        v.x -= f.x * g.x - f.y * g.y;
-        v.y -= f.x * g.y + f.y * g.x;
+        cfms(v, f, g);
         A[r][c] = v;
       }
     }

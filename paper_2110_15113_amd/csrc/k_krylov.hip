@@ -163,8 +163,7 @@ __global__ void cgs_update_kernel(const double2* __restrict__ V, long long vstri
     for (int i = 0; i < j1; ++i) {
       const double2 v = V[(long long)i * vstride + node * s + c];
       const double2 hh = hs[i * s + c];
-      wv.x -= v.x * hh.x - v.y * hh.y;
-      wv.y -= v.x * hh.y + v.y * hh.x;
+      cfms(wv, v, hh);
     }
     w[node * s + c] = wv;
     acc += wv.x * wv.x + wv.y * wv.y;
@@ -275,8 +274,7 @@ __global__ void update_x_kernel(const Z* __restrict__ Zb, long long zstride, con
   for (int i = 0; i < nj; ++i) {
     const Z zv = Zb[(long long)i * zstride + idx];
     const double2 yy = y[i * s + c];
-    acc.x += (double)zv.x * yy.x - (double)zv.y * yy.y;
-    acc.y += (double)zv.x * yy.y + (double)zv.y * yy.x;
+    cfma(acc, ccast<double2>(zv), yy);
   }
   x[idx] = acc;
 }

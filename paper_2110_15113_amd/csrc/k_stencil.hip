@@ -53,7 +53,11 @@ stencil_kernel(const C<R>* __restrict__ coef, const C<R>* __restrict__ x,
   constexpr bool UNROLL_EY = StencilChunk<R>::EY;
   constexpr int U = RC * (int)sizeof(T) / 16;   // 16-byte units per node and chunk
   constexpr int HX = TX + 2, HY = TY + 2;
-  __shared__ __align__(16) T ring[3][HY][HX][RC];
+  // x plane ring, 16-byte unit u of a node's chunk slowest within a row, rows
+  // padded to HXP units: a thread's two units sit in rows of units that are
+  // 2 HXP apart, which keeps each 16-byte LDS read free of bank conflicts
+  constexpr int HXP = HX + 2;
+  __shared__ __align__(16) float4 ring[3][HY][U][HXP];
 
   // work-group id -> (tile, chunk): the chunks of a tile on one XCD, adjacent in time
   const int bid = blockIdx.x, r = bid / NXCD;
@@ -84,7 +88,12 @@ stencil_kernel(const C<R>* __restrict__ coef, const C<R>* __restrict__ x,
 #pragma unroll
       for (int ex = -1; ex <= 1; ++ex) {
         const T a = coef[eidx(ex, ey, ez) * n + node];
-        const T* xv = &ring[slot][ly + 1 + ey][lx + 1 + ex][part * RT];
+        T xv[RT];
+        constexpr int CPU = 16 / (int)sizeof(T);   // complex values per 16-byte unit
+#pragma unroll
+        for (int c = 0; c < RT; ++c)
+          xv[c] = reinterpret_cast<const T*>(
+              &ring[slot][ly + 1 + ey][part * (RT / CPU) + c / CPU][lx + 1 + ex])[c % CPU];
 #pragma unroll
         for (int c = 0; c < RT; ++c) cfma(acc[c], a, xv[c]);
       }
@@ -117,14 +126,14 @@ stencil_kernel(const C<R>* __restrict__ coef, const C<R>* __restrict__ x,
   if constexpr (!StencilChunk<R>::PIPE) {
     // plane k + 1 staged right before plane k is computed
     auto load_plane = [&](int kk, int slot) {
-      float4* dst = reinterpret_cast<float4*>(&ring[slot][0][0][0]);
       for (int q = tid; q < NU; q += NTHREADS) {
         const int u = q % U, hn = q / U;
-        const int hi = i0 + hn % HX - 1, hj = j0 + hn / HX - 1;
+        const int hx = hn % HX, hy = hn / HX;
+        const int hi = i0 + hx - 1, hj = j0 + hy - 1;
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
         if (kk >= 0 && kk < nz && hi >= 0 && hi < nx && hj >= 0 && hj < ny)
           v = reinterpret_cast<const float4*>(x + (((long long)kk * ny + hj) * nx + hi) * s + c0)[u];
-        dst[q] = v;
+        ring[slot][hy][u][hx] = v;
       }
     };
     load_plane(k0 - 1, (k0 + 2) % 3);
@@ -153,11 +162,11 @@ stencil_kernel(const C<R>* __restrict__ coef, const C<R>* __restrict__ x,
       }
     };
     auto stash = [&](int slot) {
-      float4* dst = reinterpret_cast<float4*>(&ring[slot][0][0][0]);
 #pragma unroll
       for (int i = 0; i < PER; ++i) {
         const int q = tid + i * NTHREADS;
-        if (q < NU) dst[q] = pre[i];
+        const int u = q % U, hn = q / U;
+        if (q < NU) ring[slot][hn / HX][u][hn % HX] = pre[i];
       }
     };
     fetch(k0 - 1);

@@ -92,7 +92,6 @@ __device__ inline C<R> plane_rhs_entry(const SubDesc& sd, int k, int bwd, int q,
     const T* L = lca + sd.lca_off;
     const T* Yn = ybuf + (sd.y_off + (long long)(bwd ? k + 1 : k - 1) * sd.P) * s;
     const int ez = bwd ? 1 : -1;
-    const R sg = bwd ? (R)1 : (R)-1;
     // couplings that leave the box are stored as exact zeros in the local
     // coefficients (the restricted rows drop them), so clamped neighbour
     // indices contribute nothing and the loads need no branches
@@ -104,8 +103,8 @@ __device__ inline C<R> plane_rhs_entry(const SubDesc& sd, int k, int bwd, int q,
         const int px = min(max(qx + dx, 0), sd.sx - 1);
         const T l = L[eidx(dx, dy, ez) * nbox + node];
         const T y = Yn[(long long)(py * sd.sx + px) * s + c];
-        t.x += sg * (l.x * y.x - l.y * y.y);
-        t.y += sg * (l.x * y.y + l.y * y.x);
+        if (bwd) cfma(t, l, y);
+        else cfms(t, l, y);
       }
     }
   }
@@ -175,10 +174,8 @@ plane_rhs_f32_kernel(const SubDesc* __restrict__ subs, int nsub, int nrb, int nc
           l.x *= sg;
           l.y *= sg;
           const float4 y2 = *reinterpret_cast<const float4*>(Yn + (long long)(py * sd.sx + px) * s);
-          t0.x += l.x * y2.x - l.y * y2.y;
-          t0.y += l.x * y2.y + l.y * y2.x;
-          t1.x += l.x * y2.z - l.y * y2.w;
-          t1.y += l.x * y2.w + l.y * y2.z;
+          cfma(t0, l, make_float2(y2.x, y2.y));
+          cfma(t1, l, make_float2(y2.z, y2.w));
         }
       }
     }
