@@ -18,7 +18,8 @@
 // (the operand fragment of a 16x16x4 MFMA, and a 4x4 register block).
 //
 // The inverse is formed in place by blocked Gauss-Jordan elimination with
-// 32 x 32 pivot blocks (no pivoting; a zero or non-finite pivot is reported):
+// pivot blocks of several tiles (no pivoting; a zero or non-finite pivot is
+// reported):
 //     A_kk <- A_kk^{-1};  A_kJ <- A_kk^{-1} A_kJ;  A_IJ <- A_IJ - A_Ik A_kJ;
 //     A_Ik <- -A_Ik A_kk^{-1}.
 // The trailing update A_IJ -= A_Ik A_kJ, which carries almost all the work,
@@ -130,55 +131,64 @@ __global__ void __launch_bounds__(256) build_S_kernel(const SubDesc* subs, int k
   }
 }
 
-// ---- tile helpers: 64 threads, thread (tr, tc) owns rows 4 tr.., cols 4 tc..
-template <typename T>
-__device__ inline void load_tile_lds(const T* g, T (*lds)[TILE + 1]) {
-  for (int q = 0; q < 16; ++q) {
-    const int e = threadIdx.x + 64 * q;
-    const int c4 = e >> 7, r = (e >> 2) & 31, cl = e & 3;
-    lds[r][c4 * 4 + cl] = g[e];
-  }
-}
-// out(i, j) = sum_m X[4 tr + i][m] Y[m][4 tc + j]
-template <typename T>
-__device__ inline void tile_product(const T (*X)[TILE + 1], const T (*Y)[TILE + 1], T out[4][4]) {
-  const int tr = threadIdx.x >> 3, tc = threadIdx.x & 7;
-  for (int i = 0; i < 4; ++i)
-    for (int j = 0; j < 4; ++j) out[i][j] = czero<T>();
-  for (int m = 0; m < TILE; ++m) {
-    T xv[4], yv[4];
-    for (int i = 0; i < 4; ++i) xv[i] = X[4 * tr + i][m];
-    for (int j = 0; j < 4; ++j) yv[j] = Y[m][4 * tc + j];
-    for (int i = 0; i < 4; ++i)
-      for (int j = 0; j < 4; ++j) cfma(out[i][j], xv[i], yv[j]);
-  }
-}
-// contiguous 16-entry run of the thread's 4x4 block inside a tile
-__device__ inline int block_base() {
-  const int tr = threadIdx.x >> 3, tc = threadIdx.x & 7;
-  return (tc * TILE + tr * 4) * 4;
-}
+// ------------------------------------------------------- blocked Gauss-Jordan
+// Pivot blocks of NBT tiles (32 NBT rows); the last block of a plane may be
+// narrower.  Every pass reads and writes the whole plane matrix once, so wide
+// blocks cut the HBM traffic of the inversion; NBT is what fits the pivot
+// block in LDS for the unblocked inversion (128 x 128 FP32, 64 x 64 FP64).
+template <typename R> struct GjBlock;
+template <> struct GjBlock<float> { static constexpr int NBT = 4, THREADS = 1024; };
+template <> struct GjBlock<double> { static constexpr int NBT = 2, THREADS = 256; };
 
-// A_kk <- A_kk^{-1} by unblocked Gauss-Jordan in LDS.
+// A_kk <- A_kk^{-1} for the pivot block (nb tiles from tile kb0) by unblocked
+// Gauss-Jordan.  The block lives in registers, a 4 x 4 sub-block per thread
+// ((NB / 4)^2 threads); each pivot step publishes the pivot row and column
+// through LDS, so a step costs two barriers.
 template <typename R>
-__global__ void __launch_bounds__(256) gj_diag_kernel(const SubDesc* subs, int k, int kb,
-                                                      C<R>* fac, int* status) {
+__global__ void __launch_bounds__(GjBlock<R>::THREADS)
+gj_diag_kernel(const SubDesc* subs, int k, int kb0, C<R>* fac, int* status) {
   using T = C<R>;
-  __shared__ T A[TILE][TILE + 1];
+  constexpr int NB = TILE * GjBlock<R>::NBT;
+  constexpr int G = NB / 4;                  // thread grid edge
+  static_assert(G * G == GjBlock<R>::THREADS, "one 4 x 4 block per thread");
+  __shared__ T rowb[NB], colb[NB];
   __shared__ int bad;
   const SubDesc sd = subs[blockIdx.x];
-  if (k >= sd.sz || kb >= sd.nt) return;
-  const long long P2 = (long long)sd.P * sd.P;
-  T* tile = fac + sd.fac_off + (long long)k * P2 + tile_off(kb, kb, sd.nt);
-  for (int q = 0; q < 4; ++q) {
-    const int e = threadIdx.x + 256 * q;
-    const int c4 = e >> 7, r = (e >> 2) & 31, cl = e & 3;
-    A[r][c4 * 4 + cl] = tile[e];
+  if (k >= sd.sz || kb0 >= sd.nt) return;
+  const int nb = min(GjBlock<R>::NBT, sd.nt - kb0);
+  const int nr = nb * TILE;
+  T* base = fac + sd.fac_off + (long long)k * sd.P * sd.P;
+  const int tr = threadIdx.x / G, tc = threadIdx.x % G;
+  const int r0 = 4 * tr, c0 = 4 * tc;
+  const bool live = r0 < nr && c0 < nr;
+  // entries (r0 + i, c0 + j): tile (r / 32, c / 32), four columns contiguous
+  T a[4][4];
+  T* blk = base + tile_off(kb0 + r0 / TILE, kb0 + c0 / TILE, sd.nt);
+  if (live) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) a[i][j] = blk[in_tile((r0 + i) % TILE, (c0 % TILE) + j)];
   }
   if (threadIdx.x == 0) bad = 0;
-  __syncthreads();
-  for (int piv = 0; piv < TILE; ++piv) {
-    const T p = A[piv][piv];
+  for (int piv = 0; piv < nr; ++piv) {
+    const int pi = piv - r0, pj = piv - c0;
+    if (live) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (pi == i) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) rowb[c0 + j] = a[i][j];
+        }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (pj == j) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) colb[r0 + i] = a[i][j];
+        }
+    }
+    __syncthreads();
+    const T p = rowb[piv];
     const R mag = p.x * p.x + p.y * p.y;
     const bool ok = isfinite(p.x) && isfinite(p.y) && mag > Tiny<R>::v;
     T ip;
@@ -188,117 +198,52 @@ __global__ void __launch_bounds__(256) gj_diag_kernel(const SubDesc* subs, int k
       ip.y = -p.y / d;
     }
     if (!ok && threadIdx.x == 0) bad = 1;
-    __syncthreads();
-    if (threadIdx.x < TILE && threadIdx.x != piv) {
-      A[piv][threadIdx.x] = cmul(A[piv][threadIdx.x], ip);
-    }
-    __syncthreads();
-    for (int q = 0; q < 4; ++q) {
-      const int e = threadIdx.x + 256 * q;
-      const int r = e >> 5, c = e & 31;
-      if (r != piv && c != piv) {
-        const T f = A[r][piv];
-        const T g = A[piv][c];
-        T v = A[r][c];
-        cfms(v, f, g);
-        A[r][c] = v;
-      }
-    }
-    __syncthreads();
-    if (threadIdx.x < TILE) {
-      const int r = threadIdx.x;
-      if (r != piv) {
-        T v = cmul(A[r][piv], ip);
-        v.x = -v.x;
-        v.y = -v.y;
-        A[r][piv] = v;
-      } else {
-        A[piv][piv] = ip;
+    if (live) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = r0 + i;
+        const T f = cmul(colb[r], ip);          // A_r,piv / p
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int c = c0 + j;
+          if (r == piv) {
+            a[i][j] = (c == piv) ? ip : cmul(a[i][j], ip);
+          } else if (c == piv) {
+            a[i][j].x = -f.x;
+            a[i][j].y = -f.y;
+          } else {
+            cfms(a[i][j], f, rowb[c]);
+          }
+        }
       }
     }
     __syncthreads();
   }
-  for (int q = 0; q < 4; ++q) {
-    const int e = threadIdx.x + 256 * q;
-    const int c4 = e >> 7, r = (e >> 2) & 31, cl = e & 3;
-    tile[e] = A[r][c4 * 4 + cl];
+  if (live) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) blk[in_tile((r0 + i) % TILE, (c0 % TILE) + j)] = a[i][j];
   }
   if (threadIdx.x == 0 && bad) status[blockIdx.x] = 1;
-}
-
-// A_kJ <- A_kk^{-1} A_kJ   (J != kb)
-template <typename R>
-__global__ void __launch_bounds__(64) gj_rowpanel_kernel(const SubDesc* subs, int k, int kb,
-                                                         C<R>* fac) {
-  using T = C<R>;
-  __shared__ T D[TILE][TILE + 1];
-  __shared__ T B[TILE][TILE + 1];
-  const SubDesc sd = subs[blockIdx.y];
-  const int J = blockIdx.x;
-  if (k >= sd.sz || kb >= sd.nt || J >= sd.nt || J == kb) return;
-  T* base = fac + sd.fac_off + (long long)k * sd.P * sd.P;
-  load_tile_lds(base + tile_off(kb, kb, sd.nt), D);
-  T* dst = base + tile_off(kb, J, sd.nt);
-  load_tile_lds(dst, B);
-  __syncthreads();
-  T out[4][4];
-  tile_product(D, B, out);
-  const int o = block_base();
-  for (int i = 0; i < 4; ++i)
-    for (int j = 0; j < 4; ++j) dst[o + i * 4 + j] = out[i][j];
-}
-
-// A_IJ <- A_IJ - A_Ik A_kJ   (I, J != kb) on MFMA, one wave per 32 x 32 tile.
-// Work-group ids are mapped so that all tiles of one subdomain run on the same
-// XCD and read the pivot row and column panels from its L2.
-constexpr int NXCD = 8;
-__device__ inline void tile_map(int items, int& sub, int& item) {
-  const int b = blockIdx.x, r = b / NXCD;
-  sub = (r / items) * NXCD + b % NXCD;
-  item = r % items;
 }
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-template <typename R> struct GjUpdate;
+// One wave's 32 x 32 complex tile product on MFMA: acc += X Y with X and Y
+// 32 x 32 tiles in the tile layout (global or LDS).  visit(row, col, part,
+// value) walks the lane's share of the result.
+template <typename R> struct TileMma;
 
-// Complex FP32 on the 32x32x2 instruction.  The three tiles are fetched
-// together up front (A_Ik and A_kJ into LDS, A_IJ into registers), so a wave
-// waits for memory once.  A_Ik rows come from the tile layout (lane l: row
-// l % 32, entries 2 (l / 32), 2 (l / 32) + 1 of each 4-column run); B = A_kJ
-// is read per lane as the complex entry (k, col) and split into [Br | Bi] and
-// [-Bi | Br] by lane parity.  Real and imaginary A parts accumulate
-// separately (four independent chains).
-template <> struct GjUpdate<float> {
-  static __device__ void run(float2* __restrict__ C, const float2* __restrict__ X,
-                             const float2* __restrict__ Y) {
-    __shared__ float4 sX[512], sY[512];
-    const int lane = threadIdx.x, rr = lane & 31, h = lane >> 5;
-    const bool odd = (rr & 1) != 0;
-    float* Cf = reinterpret_cast<float*>(C);
-    float4 xr[8], yr[8];
-    float cv[2][16];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      xr[i] = reinterpret_cast<const float4*>(X)[i * 64 + lane];
-      yr[i] = reinterpret_cast<const float4*>(Y)[i * 64 + lane];
-    }
-    // accumulator item i of lane l: row 8 (i / 4) + 4 (l / 32) + i % 4, real column l % 32
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int row = 8 * (i / 4) + 4 * h + (i % 4);
-#pragma unroll
-      for (int b = 0; b < 2; ++b) cv[b][i] = Cf[2 * in_tile(row, 16 * b + (rr >> 1)) + (rr & 1)];
-    }
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      sX[i * 64 + lane] = xr[i];
-      sY[i * 64 + lane] = yr[i];
-    }
-    __syncthreads();
-    const float2* Ys = reinterpret_cast<const float2*>(sY);
-    f32x16 acc[2][2];
+// Complex FP32 on the 32x32x2 instruction: X rows come from the tile layout
+// (lane l: row l % 32, entries 2 (l / 32), 2 (l / 32) + 1 of each 4-column
+// run, one float4); Y is read per lane as the complex entry (k, col) and split
+// into [Br | Bi] and [-Bi | Br] by lane parity.  Real and imaginary X parts
+// accumulate separately (four independent chains).
+template <> struct TileMma<float> {
+  f32x16 acc[2][2];
+  __device__ void zero() {
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
@@ -306,76 +251,61 @@ template <> struct GjUpdate<float> {
         acc[b][0][j] = 0.f;
         acc[b][1][j] = 0.f;
       }
+  }
+  __device__ void mac(const float2* __restrict__ X, const float2* __restrict__ Y) {
+    const int lane = threadIdx.x & 63, rr = lane & 31, h = lane >> 5;
+    const bool odd = (rr & 1) != 0;
+    const float4* X4 = reinterpret_cast<const float4*>(X);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const float4 a = sX[q * 64 + rr * 2 + h];
+      const float4 a = X4[q * 64 + rr * 2 + h];
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
         const float ar = e ? a.z : a.x, ai = e ? a.w : a.y;
         const int kr = 4 * q + 2 * h + e;
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-          const float2 v = Ys[in_tile(kr, 16 * b + (rr >> 1))];
+          const float2 v = Y[in_tile(kr, 16 * b + (rr >> 1))];
           const float b1 = odd ? v.y : v.x, b2 = odd ? v.x : -v.y;
           acc[b][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, b1, acc[b][0], 0, 0, 0);
           acc[b][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, b2, acc[b][1], 0, 0, 0);
         }
       }
     }
+  }
+  // accumulator item i of lane l: row 8 (i / 4) + 4 (l / 32) + i % 4, real column l % 32
+  template <typename F> __device__ void visit(F f) const {
+    const int lane = threadIdx.x & 63, rr = lane & 31, h = lane >> 5;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int row = 8 * (i / 4) + 4 * h + (i % 4);
+    for (int i = 0; i < 16; ++i)
 #pragma unroll
       for (int b = 0; b < 2; ++b)
-        Cf[2 * in_tile(row, 16 * b + (rr >> 1)) + (rr & 1)] = cv[b][i] - (acc[b][0][i] + acc[b][1][i]);
-    }
+        f(8 * (i / 4) + 4 * h + (i % 4), 16 * b + (rr >> 1), rr & 1, acc[b][0][i] + acc[b][1][i]);
   }
 };
 
 // Complex FP64 on the 16x16x4 FP64 instruction (operands A[row = l % 16][k =
 // l / 16], B[k = l / 16][col = l % 16]; result item t of lane l is row
-// l / 16 + 4 t): two 16-row halves x four 8-column groups, tiles fetched up
-// front as in the FP32 form.
-template <> struct GjUpdate<double> {
-  static __device__ void run(double2* __restrict__ C, const double2* __restrict__ X,
-                             const double2* __restrict__ Y) {
-    __shared__ double2 sX[1024], sY[1024];
-    const int lane = threadIdx.x, m = lane & 15, kk = lane >> 4;
-    const bool odd = (m & 1) != 0;
-    double* Cd = reinterpret_cast<double*>(C);
-    double2 xr[16], yr[16];
-    double cv[2][4][4];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      xr[i] = X[i * 64 + lane];
-      yr[i] = Y[i * 64 + lane];
-    }
-#pragma unroll
-    for (int rs = 0; rs < 2; ++rs)
-#pragma unroll
-      for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int ns = 0; ns < 4; ++ns)
-          cv[rs][t][ns] = Cd[2 * in_tile(rs * 16 + kk + 4 * t, 8 * ns + (m >> 1)) + (m & 1)];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      sX[i * 64 + lane] = xr[i];
-      sY[i * 64 + lane] = yr[i];
-    }
-    __syncthreads();
-    f64x4 acc[2][4];
+// l / 16 + 4 t): two 16-row halves x four 8-column groups.
+template <> struct TileMma<double> {
+  f64x4 acc[2][4];
+  __device__ void zero() {
 #pragma unroll
     for (int rs = 0; rs < 2; ++rs)
 #pragma unroll
       for (int ns = 0; ns < 4; ++ns) acc[rs][ns] = f64x4{0, 0, 0, 0};
+  }
+  __device__ void mac(const double2* __restrict__ X, const double2* __restrict__ Y) {
+    const int lane = threadIdx.x & 63, m = lane & 15, kk = lane >> 4;
+    const bool odd = (m & 1) != 0;
 #pragma unroll 2
     for (int q = 0; q < 8; ++q) {
-      const double2 a0 = sX[(q * TILE + m) * 4 + kk];
-      const double2 a1 = sX[(q * TILE + 16 + m) * 4 + kk];
+      const double2 a0 = X[(q * TILE + m) * 4 + kk];
+      const double2 a1 = X[(q * TILE + 16 + m) * 4 + kk];
       const int kr = 4 * q + kk;
 #pragma unroll
       for (int ns = 0; ns < 4; ++ns) {
-        const double2 v = sY[in_tile(kr, 8 * ns + (m >> 1))];
+        const double2 v = Y[in_tile(kr, 8 * ns + (m >> 1))];
         const double b1 = odd ? v.y : v.x, b2 = odd ? v.x : -v.y;
         acc[0][ns] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.x, b1, acc[0][ns], 0, 0, 0);
         acc[0][ns] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.y, b2, acc[0][ns], 0, 0, 0);
@@ -383,56 +313,123 @@ template <> struct GjUpdate<double> {
         acc[1][ns] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.y, b2, acc[1][ns], 0, 0, 0);
       }
     }
+  }
+  template <typename F> __device__ void visit(F f) const {
+    const int lane = threadIdx.x & 63, m = lane & 15, kk = lane >> 4;
 #pragma unroll
     for (int rs = 0; rs < 2; ++rs)
 #pragma unroll
       for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int ns = 0; ns < 4; ++ns)
-          Cd[2 * in_tile(rs * 16 + kk + 4 * t, 8 * ns + (m >> 1)) + (m & 1)] =
-              cv[rs][t][ns] - acc[rs][ns][t];
+          f(rs * 16 + kk + 4 * t, 8 * ns + (m >> 1), m & 1, acc[rs][ns][t]);
   }
 };
 
+// component index of entry (row, col, part) of a tile
+__device__ inline int comp_of(int row, int col, int part) { return 2 * in_tile(row, col) + part; }
+
+// Copy one tile (1024 complex entries) into LDS with the wave's lanes.
+template <typename T>
+__device__ inline void tile_to_lds(const T* __restrict__ g, T* __restrict__ lds) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll 4
+  for (int i = 0; i < 1024 / 64; ++i) lds[i * 64 + lane] = g[i * 64 + lane];
+}
+
+// A_kJ <- A_kk^{-1} A_kJ for the pivot block (rows kb0 .. kb0 + nb - 1) and
+// one tile column J outside it: one work-group of NBT waves per (J, subdomain),
+// wave t producing tile (kb0 + t, J).  The nb input tiles of column J are
+// overwritten, so they are staged in LDS first.
+template <typename R>
+__global__ void __launch_bounds__(64 * GjBlock<R>::NBT)
+gj_rowpanel_kernel(const SubDesc* subs, int k, int kb0, C<R>* fac) {
+  using T = C<R>;
+  constexpr int NBT = GjBlock<R>::NBT;
+  __shared__ __align__(16) T sY[NBT][1024];
+  const SubDesc sd = subs[blockIdx.y];
+  const int J = blockIdx.x;
+  if (k >= sd.sz || kb0 >= sd.nt || J >= sd.nt) return;
+  const int nb = min(NBT, sd.nt - kb0);
+  if (J >= kb0 && J < kb0 + nb) return;
+  T* base = fac + sd.fac_off + (long long)k * sd.P * sd.P;
+  const int wv = threadIdx.x >> 6;
+  if (wv < nb) tile_to_lds(base + tile_off(kb0 + wv, J, sd.nt), sY[wv]);
+  __syncthreads();
+  if (wv >= nb) return;
+  TileMma<R> mm;
+  mm.zero();
+  for (int u = 0; u < nb; ++u) mm.mac(base + tile_off(kb0 + wv, kb0 + u, sd.nt), sY[u]);
+  R* out = reinterpret_cast<R*>(base + tile_off(kb0 + wv, J, sd.nt));
+  mm.visit([&](int row, int col, int part, R v) { out[comp_of(row, col, part)] = v; });
+}
+
+// A_Ik <- -A_Ik A_kk^{-1} for one tile row I outside the pivot block: one
+// work-group of NBT waves per (I, subdomain), wave t producing tile (I, kb0 + t);
+// the nb input tiles of row I are staged in LDS first.
+template <typename R>
+__global__ void __launch_bounds__(64 * GjBlock<R>::NBT)
+gj_colpanel_kernel(const SubDesc* subs, int k, int kb0, C<R>* fac) {
+  using T = C<R>;
+  constexpr int NBT = GjBlock<R>::NBT;
+  __shared__ __align__(16) T sX[NBT][1024];
+  const SubDesc sd = subs[blockIdx.y];
+  const int I = blockIdx.x;
+  if (k >= sd.sz || kb0 >= sd.nt || I >= sd.nt) return;
+  const int nb = min(NBT, sd.nt - kb0);
+  if (I >= kb0 && I < kb0 + nb) return;
+  T* base = fac + sd.fac_off + (long long)k * sd.P * sd.P;
+  const int wv = threadIdx.x >> 6;
+  if (wv < nb) tile_to_lds(base + tile_off(I, kb0 + wv, sd.nt), sX[wv]);
+  __syncthreads();
+  if (wv >= nb) return;
+  TileMma<R> mm;
+  mm.zero();
+  for (int u = 0; u < nb; ++u) mm.mac(sX[u], base + tile_off(kb0 + u, kb0 + wv, sd.nt));
+  R* out = reinterpret_cast<R*>(base + tile_off(I, kb0 + wv, sd.nt));
+  mm.visit([&](int row, int col, int part, R v) { out[comp_of(row, col, part)] = -v; });
+}
+
+// A_IJ <- A_IJ - A_Ik A_kJ (I, J outside the pivot block): one wave per tile.
+// The tile A_IJ is read into registers first; for each pivot tile u the
+// operand tiles A_Iu, A_uJ are staged in LDS (one wait for memory per pair).
+// Work-group ids are mapped so that all tiles of one subdomain run on the same
+// XCD and read the pivot row and column panels from its L2.
+constexpr int NXCD = 8;
 template <typename R>
 __global__ void __launch_bounds__(64) gj_update_kernel(const SubDesc* subs, int nsub, int max_nt,
-                                                       int k, int kb, C<R>* fac) {
-  int sub, item;
-  tile_map(max_nt * max_nt, sub, item);
+                                                       int k, int kb0, C<R>* fac) {
+  using T = C<R>;
+  __shared__ __align__(16) T sX[1024], sY[1024];
+  const int bid = blockIdx.x, r = bid / NXCD, items = max_nt * max_nt;
+  const int sub = (r / items) * NXCD + bid % NXCD, item = r % items;
   if (sub >= nsub) return;
   const SubDesc sd = subs[sub];
   const int I = item / max_nt, J = item % max_nt;
-  if (k >= sd.sz || kb >= sd.nt || I >= sd.nt || J >= sd.nt || I == kb || J == kb) return;
-  C<R>* base = fac + sd.fac_off + (long long)k * sd.P * sd.P;
-  GjUpdate<R>::run(base + tile_off(I, J, sd.nt), base + tile_off(I, kb, sd.nt),
-                   base + tile_off(kb, J, sd.nt));
-}
-
-// A_Ik <- -A_Ik A_kk^{-1}   (I != kb)
-template <typename R>
-__global__ void __launch_bounds__(64) gj_colpanel_kernel(const SubDesc* subs, int k, int kb,
-                                                         C<R>* fac) {
-  using T = C<R>;
-  __shared__ T X[TILE][TILE + 1];
-  __shared__ T D[TILE][TILE + 1];
-  const SubDesc sd = subs[blockIdx.y];
-  const int I = blockIdx.x;
-  if (k >= sd.sz || kb >= sd.nt || I >= sd.nt || I == kb) return;
+  if (k >= sd.sz || kb0 >= sd.nt || I >= sd.nt || J >= sd.nt) return;
+  const int nb = min(GjBlock<R>::NBT, sd.nt - kb0);
+  if ((I >= kb0 && I < kb0 + nb) || (J >= kb0 && J < kb0 + nb)) return;
   T* base = fac + sd.fac_off + (long long)k * sd.P * sd.P;
-  T* dst = base + tile_off(I, kb, sd.nt);
-  load_tile_lds(dst, X);
-  load_tile_lds(base + tile_off(kb, kb, sd.nt), D);
-  __syncthreads();
-  T out[4][4];
-  tile_product(X, D, out);
-  const int o = block_base();
-  for (int i = 0; i < 4; ++i)
-    for (int j = 0; j < 4; ++j) {
-      T v = out[i][j];
-      v.x = -v.x;
-      v.y = -v.y;
-      dst[o + i * 4 + j] = v;
-    }
+  R* Cr = reinterpret_cast<R*>(base + tile_off(I, J, sd.nt));
+  TileMma<R> mm;
+  mm.zero();
+  R cv[32];
+  {
+    int n = 0;
+    mm.visit([&](int row, int col, int part, R) { cv[n++] = Cr[comp_of(row, col, part)]; });
+  }
+  for (int u = 0; u < nb; ++u) {
+    tile_to_lds(base + tile_off(I, kb0 + u, sd.nt), sX);
+    tile_to_lds(base + tile_off(kb0 + u, J, sd.nt), sY);
+    __syncthreads();
+    mm.mac(sX, sY);
+    __syncthreads();
+  }
+  int n = 0;
+  mm.visit([&](int row, int col, int part, R v) {
+    Cr[comp_of(row, col, part)] = cv[n] - v;
+    ++n;
+  });
 }
 
 }  // namespace
@@ -442,18 +439,19 @@ void launch_factor_plane(const SubDesc* subs_dev, int nsub, int k, int max_nt, C
                          C<R>* tbuf, const C<R>* lca, int* status, hipStream_t st) {
   const dim3 g2(max_nt, max_nt, nsub);
   const int nsub8 = (nsub + NXCD - 1) / NXCD * NXCD;
+  constexpr int NBT = GjBlock<R>::NBT;
   if (k > 0)
     hipLaunchKernelGGL((schur_T_kernel<R>), g2, dim3(256), 0, st, subs_dev, k, fac, tbuf, lca);
   hipLaunchKernelGGL((build_S_kernel<R>), g2, dim3(256), 0, st, subs_dev, k, fac, tbuf, lca);
-  for (int kb = 0; kb < max_nt; ++kb) {
-    hipLaunchKernelGGL((gj_diag_kernel<R>), dim3(nsub), dim3(256), 0, st, subs_dev, k, kb, fac,
-                       status);
-    hipLaunchKernelGGL((gj_rowpanel_kernel<R>), dim3(max_nt, nsub), dim3(64), 0, st, subs_dev, k,
-                       kb, fac);
+  for (int kb0 = 0; kb0 < max_nt; kb0 += NBT) {
+    hipLaunchKernelGGL((gj_diag_kernel<R>), dim3(nsub), dim3(GjBlock<R>::THREADS), 0, st, subs_dev,
+                       k, kb0, fac, status);
+    hipLaunchKernelGGL((gj_rowpanel_kernel<R>), dim3(max_nt, nsub), dim3(64 * NBT), 0, st,
+                       subs_dev, k, kb0, fac);
     hipLaunchKernelGGL((gj_update_kernel<R>), dim3((unsigned)(nsub8 * max_nt * max_nt)), dim3(64),
-                       0, st, subs_dev, nsub, max_nt, k, kb, fac);
-    hipLaunchKernelGGL((gj_colpanel_kernel<R>), dim3(max_nt, nsub), dim3(64), 0, st, subs_dev, k,
-                       kb, fac);
+                       0, st, subs_dev, nsub, max_nt, k, kb0, fac);
+    hipLaunchKernelGGL((gj_colpanel_kernel<R>), dim3(max_nt, nsub), dim3(64 * NBT), 0, st,
+                       subs_dev, k, kb0, fac);
   }
 }
 
