@@ -77,6 +77,26 @@ def pml_profile(n: int, npml: int, h: float, omega: float, c_ref: float,
     return 1.0 + 1j * sigma / omega
 
 
+def interface_pml_profile(prof, n: int, lo: int, hi: int, olo: int, ohi: int, h: float,
+                          omega: float, c_ref: float, R0: float = 0.3, power: int = 2):
+    """One axis of a subdomain's stretching profile with PML transmission
+    conditions: the global half-grid profile ``prof`` plus an interface PML in
+    the overlap layers beyond the owned range [olo, ohi) on each side that is
+    not a global boundary (sec. 2.2, note on the size of overlap).  Reading
+    (the paper gives no interface profile): the outer PML's law on a layer of
+    thickness L = (olo - lo) h (resp. (hi - ohi) h), d = h (olo - xi) (resp.
+    h (xi - (ohi - 1))), sigma = sigma_max (d / L)^power with sigma_max =
+    (power + 1) c_ref ln(1 / R0) / (2 L), added to the global absorption."""
+    xi = (np.arange(2 * n + 1, dtype=np.float64) - 1.0) / 2.0
+    sig = np.zeros_like(xi)
+    for interior, L, d in ((lo > 0, (olo - lo) * h, h * np.maximum(0.0, olo - xi)),
+                           (hi < n, (hi - ohi) * h, h * np.maximum(0.0, xi - (ohi - 1)))):
+        if interior and L > 0:
+            smax = (power + 1) * c_ref * np.log(1.0 / R0) / (2.0 * L)
+            sig = sig + smax * (d / L) ** power
+    return np.asarray(prof) + 1j * sig / omega
+
+
 @dataclass
 class Fields:
     nx: int
@@ -88,6 +108,7 @@ class Fields:
     mt: np.ndarray       # (nz, ny, nx) complex squared slowness m~
     prof: tuple          # (s_x, s_y, s_z) half-grid PML profiles
     qfac: np.ndarray     # (nz, ny, nx) complex d m~ / d m  ((1 + i/2Q)^2)
+    c_ref: float = 0.0   # reference velocity of the PML profiles
 
     @property
     def shape(self):
@@ -120,7 +141,7 @@ def make_fields(vel, Q, omega, h, npml, R0=1e-3, power=2, c_ref=None,
     prof = (pml_profile(nx, npml, h, omega, cr, R0, power),
             pml_profile(ny, npml, h, omega, cr, R0, power),
             pml_profile(nz, npml, h, omega, cr, R0, power, low=not free_surface))
-    return Fields(nx, ny, nz, h, omega, w, mt, prof, qf)
+    return Fields(nx, ny, nz, h, omega, w, mt, prof, qf, cr)
 
 
 def _window(F: Fields, lo, hi):

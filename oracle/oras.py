@@ -15,11 +15,17 @@ Reading used here:
   * D_j is Boolean: 1 on the owned nodes (restricted additive Schwarz), so
     every node takes its value from its owner's local solve;
   * B_j from operator.row_coeffs(..., restrict=True) (cut fluxes + Robin);
+    or, with interface='pml' (PML transmission conditions, sec. 2.2 note on
+    the size of overlap), B_j = R_j A(s_j) R_j^T: the operator assembled with
+    the subdomain's stretching profile (global PML plus an interface PML over
+    the overlap layers, operator.interface_pml_profile), restricted to the
+    box (couplings to nodes outside the box dropped: Dirichlet truncation);
   * local solves by SciPy SuperLU, a library routine unrelated to the GPU's
     plane-block factorisation.
 """
 from __future__ import annotations
 
+import dataclasses
 from dataclasses import dataclass
 from typing import List
 
@@ -53,18 +59,42 @@ def partition(n, parts, overlap) -> List[Sub]:
     return subs
 
 
+def local_coeffs(F: op.Fields, s: Sub, interface: str = "robin", R0: float = 0.3,
+                 power: int = 2) -> np.ndarray:
+    """The 27 coefficients of the rows of B_j for subdomain ``s``."""
+    if interface == "robin":
+        return op.row_coeffs(F, s.lo, s.hi, restrict=True)
+    if interface != "pml":
+        raise ValueError(interface)
+    n = (F.nx, F.ny, F.nz)
+    prof = tuple(op.interface_pml_profile(F.prof[a], n[a], s.lo[a], s.hi[a], s.olo[a],
+                                          s.ohi[a], F.h, F.omega, F.c_ref, R0, power)
+                 for a in range(3))
+    C = op.row_coeffs(dataclasses.replace(F, prof=prof), s.lo, s.hi, restrict=False)
+    # Dirichlet truncation at the box: drop couplings to nodes outside it
+    bz, by, bx = C.shape[1:]
+    kk, jj, ii = np.meshgrid(np.arange(bz), np.arange(by), np.arange(bx), indexing="ij")
+    for ei, (ex, ey, ez) in enumerate(op.OFFSETS):
+        out = ((ii + ex < 0) | (ii + ex >= bx) | (jj + ey < 0) | (jj + ey >= by)
+               | (kk + ez < 0) | (kk + ez >= bz))
+        C[ei][out] = 0.0
+    return C
+
+
 class ORAS:
-    def __init__(self, F: op.Fields, parts, overlap):
+    def __init__(self, F: op.Fields, parts, overlap, interface: str = "robin",
+                 R0: float = 0.3, power: int = 2):
         self.F = F
+        self.interface, self.R0, self.power = interface, R0, power
         self.subs = partition((F.nx, F.ny, F.nz), parts, overlap)
         self.lus = []
         for s in self.subs:
-            B = op.csr_from_coeffs(op.row_coeffs(F, s.lo, s.hi, restrict=True))
+            B = op.csr_from_coeffs(local_coeffs(F, s, interface, R0, power))
             self.lus.append(spla.splu(B.tocsc()))
 
     def local_matrix(self, j):
         s = self.subs[j]
-        return op.csr_from_coeffs(op.row_coeffs(self.F, s.lo, s.hi, restrict=True))
+        return op.csr_from_coeffs(local_coeffs(self.F, s, self.interface, self.R0, self.power))
 
     def apply(self, v: np.ndarray) -> np.ndarray:
         """M^{-1} v for v shaped (nz, ny, nx) or (s, nz, ny, nx)."""
