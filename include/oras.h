@@ -80,6 +80,15 @@ typedef struct {
   double c_ref;        /* reference velocity; <= 0 selects the model maximum */
 } oras_pml;
 
+/* Interface condition of the subdomain matrices B_j */
+typedef enum { ORAS_IFACE_ROBIN = 0, ORAS_IFACE_PML = 1 } oras_iface_kind;
+
+typedef struct {
+  int kind;            /* ORAS_IFACE_ROBIN or ORAS_IFACE_PML */
+  int power;           /* PML: profile exponent (1..4), e.g. 2 */
+  double R0;           /* PML: designed round-trip reflection of the layer, in (0, 1), e.g. 0.3 */
+} oras_interface;
+
 typedef struct {
   int restart;         /* FGMRES restart length m (1..200) */
   int maxit;           /* maximum Arnoldi steps per column (>= 1) */
@@ -143,6 +152,19 @@ oras_status oras_set_m(oras_ctx ctx, const double* m_dev);
  * non-finite pivot returns ORAS_E_NUMERIC and leaves no factors. */
 oras_status oras_factor_subdomains(oras_ctx ctx, const int parts[3], int overlap,
                                    int factor_prec);
+
+/* As oras_factor_subdomains, with the interface condition of B_j chosen by
+ * iface (NULL: Robin, as above).  ORAS_IFACE_PML gives PML transmission
+ * conditions (sec. 2.2, note on the size of overlap: for finite differences
+ * a PML is placed in the overlap region): B_j = R_j A(s_j) R_j^T, the
+ * operator assembled with the subdomain's stretching profile and restricted
+ * to the box (Dirichlet beyond it).  The profile is the outer PML plus, on
+ * each interior side, a layer over the overlap nodes beyond the owned range:
+ * sigma = sigma_max (d / L)^power, d the distance from the owned range,
+ * L = overlap h, sigma_max = (power + 1) c_ref ln(1 / R0) / (2 L) with the
+ * c_ref of the assembly.  PML needs overlap >= 1. */
+oras_status oras_factor_subdomains_ex(oras_ctx ctx, const int parts[3], int overlap,
+                                      int factor_prec, const oras_interface* iface);
 
 /* Solve A x_c = b_c for nrhs columns with pseudo-block right-preconditioned
  * FGMRES (sec. 2.1, sec. 2.2): FP64 Arnoldi basis, classical Gram-Schmidt,

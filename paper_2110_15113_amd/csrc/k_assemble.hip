@@ -48,17 +48,49 @@ __device__ inline long long clamp_index(const int p[3], const int n[3]) {
   int z = min(max(p[2], 0), n[2] - 1);
   return ((long long)z * n[1] + y) * n[0] + x;
 }
-__device__ inline double2 prof_at(const OpView& V, int a, int t) {
-  return a == 0 ? V.px[t] : (a == 1 ? V.py[t] : V.pz[t]);
+// Interface PML of one subdomain (PML transmission conditions, sec. 2.2 note
+// on the size of overlap): extra absorption over the overlap layers beyond the
+// owned range on each interior side, sigma = smax (d / L)^power with d the
+// distance from the owned range.  smax = 0 on sides without a layer.
+struct SubPml {
+  int olo[3], ohi[3];
+  double smax_lo[3], smax_hi[3], L_lo[3], L_hi[3];
+  double h, inv_omega;
+  int power;
+};
+
+// Stretching factor s_a at half-grid index t (xi = (t - 1) / 2): the outer PML
+// profile, plus the subdomain's interface layer when sp is given.
+__device__ inline double2 prof_at(const OpView& V, int a, int t, const SubPml* sp = nullptr) {
+  double2 s = a == 0 ? V.px[t] : (a == 1 ? V.py[t] : V.pz[t]);
+  if (sp) {
+    const double xi = 0.5 * (t - 1);
+    double sig = 0.0;
+    const double d[2] = {sp->h * fmax(0.0, sp->olo[a] - xi), sp->h * fmax(0.0, xi - (sp->ohi[a] - 1))};
+    const double L[2] = {sp->L_lo[a], sp->L_hi[a]};
+    const double sm[2] = {sp->smax_lo[a], sp->smax_hi[a]};
+    for (int side = 0; side < 2; ++side) {
+      if (sm[side] <= 0.0) continue;
+      const double r = d[side] / L[side];
+      double f = 1.0;
+      for (int q = 0; q < sp->power; ++q) f *= r;
+      sig += sm[side] * f;
+    }
+    s.y += sig * sp->inv_omega;
+  }
+  return s;
 }
-__device__ inline double2 node_S(const OpView& V, const int p[3]) {
-  return cmul(cmul(V.px[2 * p[0] + 1], V.py[2 * p[1] + 1]), V.pz[2 * p[2] + 1]);
+__device__ inline double2 node_S(const OpView& V, const int p[3], const SubPml* sp = nullptr) {
+  return cmul(cmul(prof_at(V, 0, 2 * p[0] + 1, sp), prof_at(V, 1, 2 * p[1] + 1, sp)),
+              prof_at(V, 2, 2 * p[2] + 1, sp));
 }
 
 // The 27 coefficients of the row of node `pos`.  restrict = true builds B_j
-// for the box [lo, hi); otherwise A.
+// for the box [lo, hi) with Robin interfaces (cut fluxes, impedance term);
+// otherwise the row of A, assembled with the interface PML `sp` when given
+// (the caller then drops the couplings that leave the box).
 __device__ void row_coeffs(const OpView& V, const int pos[3], const int lo[3], const int hi[3],
-                           bool restrict_, double2 out[27]) {
+                           bool restrict_, double2 out[27], const SubPml* sp = nullptr) {
   const int n[3] = {V.nx, V.ny, V.nz};
   for (int e = 0; e < 27; ++e) out[e] = make_double2(0.0, 0.0);
   const double inv_h2 = 1.0 / (V.h * V.h);
@@ -98,7 +130,7 @@ __device__ void row_coeffs(const OpView& V, const int pos[3], const int lo[3], c
       double2 sv[3];
       for (int a = 0; a < 3; ++a) {
         int t = (mask & (1 << a)) ? 2 * pos[a] + sigma[a] + 1 : 2 * pos[a] + 1;
-        sv[a] = prof_at(V, a, t);
+        sv[a] = prof_at(V, a, t, sp);
       }
       const double2 S = cmul(cmul(sv[0], sv[1]), sv[2]);
       double2 W[3];
@@ -133,7 +165,7 @@ __device__ void row_coeffs(const OpView& V, const int pos[3], const int lo[3], c
   const long long ii = ((long long)pos[2] * n[1] + pos[1]) * n[0] + pos[0];
   const double om2 = V.omega * V.omega;
   const double2 mti = V.mt[ii];
-  const double2 Si = node_S(V, pos);
+  const double2 Si = node_S(V, pos, sp);
   {
     double2 d = cscale(cmul(mti, Si), om2 * V.w7[ii * 7 + 3]);
     out[13] = cadd(out[13], d);
@@ -149,7 +181,7 @@ __device__ void row_coeffs(const OpView& V, const int pos[3], const int lo[3], c
         const int widx = 3 + abs(ex) + abs(ey) + abs(ez);
         const double wm = 0.5 * (V.w7[ii * 7 + widx] + V.w7[jj * 7 + widx]);
         double2 mm = cscale(cadd(mti, V.mt[jj]), 0.5);
-        double2 ss = cscale(cadd(Si, node_S(V, q)), 0.5);
+        double2 ss = cscale(cadd(Si, node_S(V, q, sp)), 0.5);
         double2 mu = cscale(cmul(mm, ss), wm * om2);
         const int e = eidx(ex, ey, ez);
         out[e] = cadd(out[e], mu);
@@ -190,7 +222,7 @@ __global__ void assemble_global_kernel(OpView V, double2* coef128, float2* coef6
 }
 
 template <typename T>
-__global__ void assemble_local_kernel(OpView V, const SubDesc* subs, T* lca) {
+__global__ void assemble_local_kernel(OpView V, const SubDesc* subs, T* lca, IfaceView ifc) {
   const SubDesc sd = subs[blockIdx.y];
   const long long nbox = (long long)sd.sx * sd.sy * sd.sz;
   const long long loc = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -200,7 +232,31 @@ __global__ void assemble_local_kernel(OpView V, const SubDesc* subs, T* lca) {
   pos[1] = sd.lo[1] + (int)((loc / sd.sx) % sd.sy);
   pos[2] = sd.lo[2] + (int)(loc / ((long long)sd.sx * sd.sy));
   double2 c[27];
-  row_coeffs(V, pos, sd.lo, sd.hi, true, c);
+  if (ifc.kind == ORAS_IFACE_PML) {
+    // B_j = R_j A(s_j) R_j^T: the operator with the subdomain's stretching
+    // profile, couplings to nodes outside the box dropped (Dirichlet beyond it)
+    const int n[3] = {V.nx, V.ny, V.nz};
+    SubPml sp;
+    sp.h = V.h;
+    sp.inv_omega = 1.0 / V.omega;
+    sp.power = ifc.power;
+    for (int a = 0; a < 3; ++a) {
+      sp.olo[a] = sd.olo[a];
+      sp.ohi[a] = sd.ohi[a];
+      sp.L_lo[a] = (sd.olo[a] - sd.lo[a]) * V.h;
+      sp.L_hi[a] = (sd.hi[a] - sd.ohi[a]) * V.h;
+      const double num = (ifc.power + 1) * ifc.c_ref * log(1.0 / ifc.R0) * 0.5;
+      sp.smax_lo[a] = (sd.lo[a] > 0 && sp.L_lo[a] > 0) ? num / sp.L_lo[a] : 0.0;
+      sp.smax_hi[a] = (sd.hi[a] < n[a] && sp.L_hi[a] > 0) ? num / sp.L_hi[a] : 0.0;
+    }
+    row_coeffs(V, pos, sd.lo, sd.hi, false, c, &sp);
+    for (int e = 0; e < 27; ++e) {
+      const int q[3] = {pos[0] + e % 3 - 1, pos[1] + (e / 3) % 3 - 1, pos[2] + e / 9 - 1};
+      if (!in_box(q, sd.lo, sd.hi)) c[e] = make_double2(0.0, 0.0);
+    }
+  } else {
+    row_coeffs(V, pos, sd.lo, sd.hi, true, c);
+  }
   T* out = lca + sd.lca_off;
   for (int e = 0; e < 27; ++e) {
     T v;
@@ -303,15 +359,15 @@ void launch_assemble_global(const OpView& op, double2* coef128, float2* coef64, 
 }
 
 void launch_assemble_local(const OpView& op, const SubDesc* subs_dev, int nsub, long long max_box,
-                           void* lca, int prec, hipStream_t s) {
+                           void* lca, int prec, const IfaceView& ifc, hipStream_t s) {
   const int bs = 128;
   dim3 grid((unsigned)((max_box + bs - 1) / bs), (unsigned)nsub);
   if (prec == ORAS_C64)
     hipLaunchKernelGGL(assemble_local_kernel<float2>, grid, dim3(bs), 0, s, op, subs_dev,
-                       (float2*)lca);
+                       (float2*)lca, ifc);
   else
     hipLaunchKernelGGL(assemble_local_kernel<double2>, grid, dim3(bs), 0, s, op, subs_dev,
-                       (double2*)lca);
+                       (double2*)lca, ifc);
 }
 
 void launch_fields(const double* vel, const double* q, const double* m_override, const double* wtab,

@@ -472,8 +472,32 @@ oras_status oras_set_m(oras_ctx c, const double* m_dev) {
 }
 
 oras_status oras_factor_subdomains(oras_ctx c, const int parts[3], int overlap, int factor_prec) {
+  return oras_factor_subdomains_ex(c, parts, overlap, factor_prec, nullptr);
+}
+
+oras_status oras_factor_subdomains_ex(oras_ctx c, const int parts[3], int overlap, int factor_prec,
+                                      const oras_interface* iface) {
   if (!c) return ORAS_E_ARG;
   if (!parts) return fail(c, ORAS_E_ARG, "null parts");
+  IfaceView ifc;
+  ifc.kind = ORAS_IFACE_ROBIN;
+  ifc.power = 2;
+  ifc.R0 = 0.3;
+  ifc.c_ref = 0.0;
+  if (iface) {
+    if (iface->kind != ORAS_IFACE_ROBIN && iface->kind != ORAS_IFACE_PML)
+      return fail(c, ORAS_E_ARG, "interface kind must be ORAS_IFACE_ROBIN or ORAS_IFACE_PML");
+    if (iface->kind == ORAS_IFACE_PML) {
+      if (!(iface->R0 > 0.0 && iface->R0 < 1.0))
+        return fail(c, ORAS_E_ARG, "interface PML R0 must lie in (0, 1)");
+      if (iface->power < 1 || iface->power > 4)
+        return fail(c, ORAS_E_ARG, "interface PML power must be 1..4");
+      if (overlap < 1) return fail(c, ORAS_E_ARG, "PML interfaces need overlap >= 1");
+      ifc.kind = ORAS_IFACE_PML;
+      ifc.power = iface->power;
+      ifc.R0 = iface->R0;
+    }
+  }
   if (factor_prec != ORAS_C64 && factor_prec != ORAS_C128)
     return fail(c, ORAS_E_ARG, "factor_prec must be ORAS_C64 or ORAS_C128");
   if (overlap < 0 || overlap > 8) return fail(c, ORAS_E_ARG, "overlap must be 0..8");
@@ -548,8 +572,9 @@ oras_status oras_factor_subdomains(oras_ctx c, const int parts[3], int overlap, 
                             hipMemcpyHostToDevice, c->stream));
   launch_zero(c->status.p, subs.size() * sizeof(int), c->stream);
   const double t0 = now();
+  ifc.c_ref = c->c_ref;
   launch_assemble_local(opview(c), c->subs_dev.as<SubDesc>(), (int)subs.size(), max_box, c->lca.p,
-                        factor_prec, c->stream);
+                        factor_prec, ifc, c->stream);
   HIP_TRY(c, hipGetLastError());
   for (int k = 0; k < max_sz; ++k) {
     if (factor_prec == ORAS_C64)

@@ -96,8 +96,15 @@ struct SubDesc {
 // ------------------------------------------------------------- launchers --
 // Assembly
 void launch_assemble_global(const OpView& op, double2* coef128, float2* coef64, hipStream_t s);
+// Interface condition of the local matrices (kind ORAS_IFACE_ROBIN or
+// ORAS_IFACE_PML; the PML layer law uses c_ref, R0 and power).
+struct IfaceView {
+  int kind;
+  int power;
+  double c_ref, R0;
+};
 void launch_assemble_local(const OpView& op, const SubDesc* subs_dev, int nsub, long long max_box,
-                           void* lca, int prec, hipStream_t s);
+                           void* lca, int prec, const IfaceView& ifc, hipStream_t s);
 void launch_fields(const double* vel, const double* q, const double* m_override, const double* wtab,
                    int tab_count, double g0, double dg, int nx, int ny, int nz, double h,
                    double omega, double* w7, double2* qfac, double2* mt, hipStream_t s,

@@ -43,6 +43,13 @@ class Pml(ct.Structure):
     _fields_ = [("R0", ct.c_double), ("power", ct.c_int), ("c_ref", ct.c_double)]
 
 
+class Interface(ct.Structure):
+    _fields_ = [("kind", ct.c_int), ("power", ct.c_int), ("R0", ct.c_double)]
+
+
+IFACE_ROBIN, IFACE_PML = 0, 1
+
+
 class SolveOpts(ct.Structure):
     _fields_ = [("restart", ct.c_int), ("maxit", ct.c_int), ("flags", ct.c_int),
                 ("reserved", ct.c_int)]
@@ -67,6 +74,8 @@ SIGNATURES = {
                                  ct.c_double, ct.POINTER(Pml), ct.c_int]),
     "oras_set_m": (ct.c_int, [ct.c_void_p, ct.c_void_p]),
     "oras_factor_subdomains": (ct.c_int, [ct.c_void_p, ct.POINTER(ct.c_int), ct.c_int, ct.c_int]),
+    "oras_factor_subdomains_ex": (ct.c_int, [ct.c_void_p, ct.POINTER(ct.c_int), ct.c_int, ct.c_int,
+                                             ct.c_void_p]),
     "oras_solve": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_double,
                               ct.POINTER(SolveOpts), ct.POINTER(SolveInfo)]),
     "oras_point_sources": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int,
@@ -205,9 +214,16 @@ class Solver:
         _need(m, torch.float64, self.device, self.shape, name="m")
         self._check(lib().oras_set_m(self._ctx, _ptr(m)))
 
-    def factor(self, parts: Sequence[int], overlap: int = 2, prec: int = C128):
+    def factor(self, parts: Sequence[int], overlap: int = 2, prec: int = C128,
+               interface: str = "robin", R0: float = 0.3, power: int = 2):
+        """interface: "robin" (impedance faces) or "pml" (PML transmission
+        conditions over the overlap layers; R0, power: the layer's law)."""
         arr = (ct.c_int * 3)(*[int(p) for p in parts])
-        self._check(lib().oras_factor_subdomains(self._ctx, arr, int(overlap), int(prec)))
+        if interface not in ("robin", "pml"):
+            raise ValueError("interface must be 'robin' or 'pml'")
+        ifc = Interface(IFACE_PML if interface == "pml" else IFACE_ROBIN, int(power), float(R0))
+        self._check(lib().oras_factor_subdomains_ex(self._ctx, arr, int(overlap), int(prec),
+                                                    ct.addressof(ifc)))
 
     def timings(self):
         ta, tf = ct.c_double(), ct.c_double()

@@ -16,7 +16,7 @@ def solver():
     return oras
 
 
-def setup(w, prec=2, parts=None, overlap=None, fprec=None):
+def setup(w, prec=2, parts=None, overlap=None, fprec=None, interface="robin"):
     """Assemble (and optionally factor) workload ``w`` on the GPU."""
     oras = solver()
     S = oras.Solver(0)
@@ -25,7 +25,8 @@ def setup(w, prec=2, parts=None, overlap=None, fprec=None):
     Q = None if w.Q is None else torch.as_tensor(w.Q, device=dev)
     S.assemble(vel, w.h, w.npml, w.omega, Q, prec=prec)
     if parts is not None:
-        S.factor(parts, w.overlap if overlap is None else overlap, prec if fprec is None else fprec)
+        S.factor(parts, w.overlap if overlap is None else overlap, prec if fprec is None else fprec,
+                 interface=interface)
     return S
 
 

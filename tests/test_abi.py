@@ -23,7 +23,7 @@ def test_library_exports_every_declared_symbol():
     L = oras.lib()
     hdr = open(os.path.join(ROOT, "include", "oras.h")).read()
     names = set(re.findall(r"\b(oras_[a-z_A-Z]+)\s*\(", hdr))
-    assert len(names) >= 17
+    assert len(names) >= 18
     for name in names:
         assert hasattr(L, name), name
     assert names <= set(oras.SIGNATURES), names - set(oras.SIGNATURES)
@@ -69,6 +69,14 @@ def test_host_only_context_validates_before_device():
         assert L.oras_factor_subdomains(ctx, parts, 2, 2) == 2
         assert L.oras_factor_subdomains(ctx, parts, 9, 2) == 1
         assert L.oras_factor_subdomains(ctx, parts, 2, 5) == 1
+        # interface descriptors are checked before the state
+        pml = oras.Interface(oras.IFACE_PML, 2, 0.3)
+        assert L.oras_factor_subdomains_ex(ctx, parts, 2, 2, ct.byref(pml)) == 2
+        for bad_if, ov in ((oras.Interface(7, 2, 0.3), 2), (oras.Interface(oras.IFACE_PML, 2, 1.5), 2),
+                           (oras.Interface(oras.IFACE_PML, 0, 0.3), 2),
+                           (oras.Interface(oras.IFACE_PML, 2, 0.3), 0)):
+            assert L.oras_factor_subdomains_ex(ctx, parts, ov, 2, ct.byref(bad_if)) == 1
+        assert L.oras_factor_subdomains_ex(ctx, parts, 2, 2, None) == 2
         opts = oras.SolveOpts(30, 100, 0, 0)
         assert L.oras_solve(ctx, fake, fake, 1, 1e-6, ct.byref(opts), None) == 2
         assert L.oras_solve(ctx, fake, fake, 1, 0.0, ct.byref(opts), None) == 1

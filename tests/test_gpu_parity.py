@@ -75,6 +75,33 @@ def test_apply_M_matches_oracle(case):
     assert rel(got64, ref) < 1e-3, rel(got64, ref)
 
 
+PML_CASES = [
+    dict(n=(16, 16, 16), parts=(2, 2, 2), ov=2, npml=3, q=100.0, nrhs=2),
+    dict(n=(19, 17, 15), parts=(2, 3, 2), ov=3, npml=2, q=50.0, nrhs=9),
+    dict(n=(22, 14, 18), parts=(3, 1, 2), ov=1, npml=2, q=None, nrhs=20),
+]
+
+
+@pytest.mark.parametrize("case", PML_CASES)
+def test_apply_M_pml_interfaces_matches_oracle(case):
+    """PML transmission conditions: B_j = R_j A(s_j) R_j^T with the interface
+    layer over the overlap (paper sec. 2.2, note on the size of overlap)."""
+    need_gpu()
+    w = wl.small_random(case["n"], npml=case["npml"], q=case["q"], seed=7,
+                        parts=case["parts"], overlap=case["ov"])
+    say(f"apply_M pml {case}")
+    F = oracle_fields(w)
+    M = ooras.ORAS(F, case["parts"], case["ov"], interface="pml")
+    x = rand_field((w.nz, w.ny, w.nx), case["nrhs"], 17)
+    ref = M.apply(x)
+    S = setup(w, prec=2, parts=case["parts"], overlap=case["ov"], interface="pml")
+    got = S.apply_M(to_dev(x, S)).cpu().numpy()
+    assert rel(got, ref) < 1e-9, rel(got, ref)
+    S64 = setup(w, prec=1, parts=case["parts"], overlap=case["ov"], interface="pml")
+    got64 = S64.apply_M(to_dev(x, S64)).cpu().numpy()
+    assert rel(got64, ref) < 1e-3, rel(got64, ref)
+
+
 def test_subdomain_boxes_match_oracle_partition():
     need_gpu()
     w = wl.small_random((19, 17, 15), npml=2, seed=3)

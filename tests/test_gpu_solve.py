@@ -36,6 +36,25 @@ def test_config1_fp64_matches_direct_and_oracle_fgmres():
     assert ok and abs(int(r.iters[0]) - it) <= 1, (r.iters, it)
 
 
+@pytest.mark.parametrize("ov", [2, 3])
+def test_config1_pml_interfaces_match_direct_and_oracle_fgmres(ov):
+    need_gpu()
+    c = wl.config1()
+    say(f"config1 fp64, PML interfaces, overlap {ov}")
+    F = oracle_fields(c)
+    b = op.point_sources(F, c.sources)
+    u, A = _direct(c, b)
+    S = setup(c, prec=2, parts=c.parts, overlap=ov, interface="pml")
+    r = S.solve(to_dev(b, S), c.tol, restart=c.restart)
+    x = r.x.cpu().numpy()
+    assert r.converged.all()
+    assert rel(x, u) < 1e-6, rel(x, u)
+    M = ooras.ORAS(F, c.parts, ov, interface="pml")
+    _, it, ok, _ = krylov.fgmres(lambda v: A @ v, lambda v: M.apply(v.reshape(F.shape)).reshape(-1),
+                                 b[0].ravel(), c.tol, c.restart, c.maxit)
+    assert ok and abs(int(r.iters[0]) - it) <= 1, (r.iters, it)
+
+
 @pytest.mark.parametrize("mixed", [False, True])
 def test_multi_rhs_small_model(mixed):
     need_gpu()
