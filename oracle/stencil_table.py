@@ -128,6 +128,18 @@ def table() -> np.ndarray:
     return _TABLE
 
 
+def lookup_slope(G: np.ndarray, tab: np.ndarray | None = None) -> np.ndarray:
+    """d lookup / dG: the slope of the table segment the interpolation uses,
+    zero where the lookup clamps (G outside the table range); (..., 7)."""
+    tab = table() if tab is None else tab
+    t = (np.asarray(G, dtype=np.float64) - G_MIN) / G_STEP
+    inside = (t > 0.0) & (t < G_COUNT - 1.0)
+    tc = np.clip(t, 0.0, G_COUNT - 1.0)
+    i0 = np.minimum(np.floor(tc).astype(np.int64), G_COUNT - 2)
+    slope = (tab[i0 + 1] - tab[i0]) / G_STEP
+    return np.where(inside[..., None], slope, 0.0)
+
+
 def lookup(G: np.ndarray, tab: np.ndarray | None = None) -> np.ndarray:
     """Linear interpolation in G (clamped to the table range); returns
     (..., 7)."""

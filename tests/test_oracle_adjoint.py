@@ -2,7 +2,7 @@
 paper sec. 1 and sec. 4)."""
 import numpy as np
 
-from oracle import adjoint, direct, operator as op
+from oracle import adjoint, direct, operator as op, stencil_table as st
 from paper_2110_15113_amd import workloads as wl
 
 
@@ -74,3 +74,72 @@ def test_sample_spread_are_transposes():
     U = rng.normal(size=(2, 5, 6, 7)) + 1j * rng.normal(size=(2, 5, 6, 7))
     G = rng.normal(size=(2, 3)) + 1j * rng.normal(size=(2, 3))
     assert abs(np.vdot(G, adjoint.sample(U, rec)) - np.vdot(adjoint.spread(G, rec, (5, 6, 7)), U)) < 1e-12
+
+
+def _mu_A_u(F, U, MU):
+    A = op.assemble(F)
+    return sum(np.vdot(MU[s].ravel(), A @ U[s].ravel()) for s in range(U.shape[0]))
+
+
+def test_weight_sensitivity_matches_assembly_derivative():
+    """A is linear in every stencil weight of every node, so a central
+    difference of mu^H A(w) u in one weight is exact up to rounding; nodes on
+    the grid boundary check the ghost-clamp distribution."""
+    import dataclasses
+    w = wl.small_random((7, 6, 8), npml=2, q=30.0, seed=5)
+    F = op.make_fields(w.vel, w.Q, w.omega, w.h, w.npml)
+    rng = np.random.default_rng(4)
+    U = rng.normal(size=(2,) + F.shape) + 1j * rng.normal(size=(2,) + F.shape)
+    MU = rng.normal(size=(2,) + F.shape) + 1j * rng.normal(size=(2,) + F.shape)
+    H = adjoint.weight_sensitivity(F, U, MU)
+    nodes = [(0, 0, 0), (3, 2, 4), (6, 5, 7), (0, 3, 5), (5, 0, 2)]
+    for (i, j, k) in nodes:
+        for kk in range(7):
+            eps = 1e-3
+            wp = F.w.copy()
+            wm = F.w.copy()
+            wp[k, j, i, kk] += eps
+            wm[k, j, i, kk] -= eps
+            fd = (_mu_A_u(dataclasses.replace(F, w=wp), U, MU)
+                  - _mu_A_u(dataclasses.replace(F, w=wm), U, MU)) / (2 * eps)
+            assert abs(fd - H[k, j, i, kk]) <= 1e-9 * max(abs(fd), 1e-30) + 1e-12 * np.abs(H).max(), \
+                ((i, j, k), kk, fd, H[k, j, i, kk])
+
+
+def test_table_slope_matches_lookup_differences():
+    G = np.array([3.1, 5.1, 9.37, 17.1, 31.8, 47.9])   # inside segments (knots every 0.25)
+    s = st.lookup_slope(G)
+    for d in (1e-7,):
+        fd = (st.lookup(G + d) - st.lookup(G - d)) / (2 * d)
+        assert np.abs(fd - s).max() <= 1e-6 * np.abs(s).max()
+    assert np.all(st.lookup_slope(np.array([2.0, 50.0])) == 0.0)   # clamped outside the table
+
+
+def _J_follow(w, rec, m, d_obs, cref):
+    F = adjoint.fields_from_m(m, w.Q, w.omega, w.h, w.npml, cref)
+    A = op.assemble(F)
+    J, _, U, MU = adjoint.misfit_and_gradient(F, w.sources, rec, d_obs,
+                                              lambda b: direct.solve(A, F.shape, b))
+    return J, adjoint.gradient_exact(F, U, MU, m)
+
+
+def test_exact_gradient_matches_finite_differences():
+    """Weights following m (the lambda-adaptive stencil picks them from the
+    local G, sec. 2.3): the exact gradient against central differences of
+    the misfit; the frozen-weight gradient does not satisfy this test."""
+    for q in (None, 40.0):
+        w, rec, m0 = _setup(q)
+        cref = float(w.vel.max())
+        rng = np.random.default_rng(11)
+        d_obs = rng.normal(size=(2, len(rec))) * 1e-5 + 1j * rng.normal(size=(2, len(rec))) * 1e-5
+        J0, g = _J_follow(w, rec, m0, d_obs, cref)
+        gnorm = np.linalg.norm(g)
+        for t in range(4):
+            dm = rng.normal(size=m0.shape) * m0
+            dm /= np.abs(dm).max()
+            eps = 1e-4 * np.abs(m0).max()
+            Jp, _ = _J_follow(w, rec, m0 + eps * dm, d_obs, cref)
+            Jm, _ = _J_follow(w, rec, m0 - eps * dm, d_obs, cref)
+            fd = (Jp - Jm) / (2 * eps)
+            an = float(np.sum(g * dm))
+            assert abs(fd - an) <= 1e-5 * gnorm * np.linalg.norm(dm), (q, t, fd, an)
