@@ -142,6 +142,16 @@ oras_status oras_assemble(oras_ctx ctx, const oras_grid* grid, const double* vel
  * oras_assemble.  Used by the differentiable forward map.  Drops factors. */
 oras_status oras_set_m(oras_ctx ctx, const double* m_dev);
 
+/* Flags of oras_set_m_ex and oras_gradient_ex */
+#define ORAS_WEIGHTS_FOLLOW_M 1  /* set_m: recompute the stencil weights from m
+                                    (G = 2 pi / (omega h sqrt(m)), sec. 2.3) */
+#define ORAS_GRAD_WEIGHTS 1      /* gradient: add the weights' dependence on m */
+
+/* As oras_set_m; with ORAS_WEIGHTS_FOLLOW_M the lambda-adaptive weights are
+ * picked again from each node's G at the new m (the attenuation factor and
+ * PML stay those of the last oras_assemble).  flags = 0 is oras_set_m. */
+oras_status oras_set_m_ex(oras_ctx ctx, const double* m_dev, int flags);
+
 /* Partition the grid into parts[0] x parts[1] x parts[2] cuboids (floor
  * split), extend each by `overlap` layers on interior sides (sec. 2.2:
  * overlapping cuboids), assemble every local matrix B_j with Robin interface
@@ -196,6 +206,16 @@ oras_status oras_spread(oras_ctx ctx, const void* d_dev, int nrhs, const int* re
  * mu (A^H mu = P^T dJ/dd); stencil weights frozen (FWI use, sec. 1, sec. 4). */
 oras_status oras_gradient(oras_ctx ctx, const void* u_dev, const void* mu_dev, int nrhs,
                           double* g_dev);
+
+/* As oras_gradient; with ORAS_GRAD_WEIGHTS the gradient also carries the
+ * stencil weights' dependence on m (they are picked from the local G, sec.
+ * 2.3): -Re sum_k H_k dw_k/dm, H_k = sum_c d(mu_c^H A u_c)/dw_k, dw/dm the
+ * weight table's slope times dG/dm = -G / (2 m).  This is the gradient of the
+ * map whose weights follow m, so it needs weights that match the current m
+ * (after oras_assemble, or oras_set_m_ex with ORAS_WEIGHTS_FOLLOW_M):
+ * otherwise ORAS_E_STATE.  Uses scratch of about 7 n doubles. */
+oras_status oras_gradient_ex(oras_ctx ctx, const void* u_dev, const void* mu_dev, int nrhs,
+                             int flags, double* g_dev);
 
 /* Test hooks running the same kernels as the solver.
  * oras_apply_A: y = A x in precision prec (ORAS_C64 needs stencil_prec C64).

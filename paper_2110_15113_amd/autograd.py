@@ -9,9 +9,12 @@ g = dL/dRe(d) + i dL/dIm(d):
     mu_s = A^{-H} P^T g_s      (A^H = conj(A): a conjugate solve, same factors)
     dL/dm_i = -Re sum_s mu_s^H (dA/dm_i) u_s
 
-with the stencil weights, PML and Q frozen at the last ``assemble`` (so only
-the mass term depends on m).  Every step runs in the HIP library; this module
-wires the calls into torch's autograd.
+By default the stencil weights, PML and Q stay frozen at the last
+``assemble`` (so only the mass term depends on m).  With weights="follow" the
+lambda-adaptive weights are picked again from the local G at every m (sec.
+2.3) and the gradient adds their derivative through the table slope (the
+exact gradient of that discretisation); the PML and Q stay fixed.  Every step
+runs in the HIP library; this module wires the calls into torch's autograd.
 
 Memory policy: the forward wavefields are kept for the backward pass when
 their size fits ``save_budget_bytes``; otherwise the backward recomputes them
@@ -40,6 +43,7 @@ class ForwardSetup:
     maxit: int = 2000
     save_budget_bytes: float = 32e9
     stats: Optional[dict] = None
+    weights: str = "frozen"       # or "follow": weights picked from G(m)
 
 
 def _prepare(fs: ForwardSetup, m: torch.Tensor):
@@ -49,7 +53,7 @@ def _prepare(fs: ForwardSetup, m: torch.Tensor):
     # tensor while (address, version) identifies the factors
     key = (m.data_ptr(), m._version)
     if getattr(S, "_m_key", None) != key:
-        S.set_m(m.detach().contiguous())
+        S.set_m(m.detach().contiguous(), weights=fs.weights)
         S.factor(fs.parts, fs.overlap, fs.prec)
         S._m_key = key
         S._m_ref = m
@@ -96,7 +100,7 @@ class HelmholtzData(torch.autograd.Function):
             raise RuntimeError("adjoint solve did not converge")
         if fs.stats is not None:
             fs.stats.setdefault("adjoint_iters", []).append(r.iters.tolist())
-        grad = S.gradient(u, r.x)
+        grad = S.gradient(u, r.x, weights=fs.weights == "follow")
         return grad, None
 
 

@@ -273,7 +273,8 @@ __global__ void fields_kernel(const double* vel, const double* q, const double* 
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   if (!keep_weights) {
-    const double c = vel[i];
+    // weights from the velocity, or (no velocity given) from the squared slowness
+    const double c = vel ? vel[i] : 1.0 / sqrt(m_override[i]);
     const double G = 2.0 * M_PI * c / (omega * h);
     double t = (G - g0) / dg;
     t = fmin(fmax(t, 0.0), (double)(tab_count - 1));
@@ -284,7 +285,7 @@ __global__ void fields_kernel(const double* vel, const double* q, const double* 
       w7[i * 7 + k] = (1.0 - f) * wtab[i0 * 7 + k] + f * wtab[(i0 + 1) * 7 + k];
   }
   double2 qf;
-  if (keep_weights) {
+  if (keep_weights || !vel) {   // set_m: the attenuation factor of the assembly stays
     qf = qfac[i];
   } else {
     qf = make_double2(1.0, 0.0);

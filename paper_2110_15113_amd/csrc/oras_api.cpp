@@ -67,7 +67,8 @@ struct oras_ctx_s {
   int npml = 0, free_surface = 0;
   double c_ref = 0;
   int stencil_prec = ORAS_C128;
-  DevBuf w7, mt, qf, px, py, pz, coef128, coef64, wtab, scratch8;
+  DevBuf w7, mt, qf, px, py, pz, coef128, coef64, wtab, scratch8, gradw;
+  bool weights_match_m = false;   // the stencil weights are those of the current m
   double t_assemble = 0;
 
   // factors
@@ -116,7 +117,7 @@ struct oras_ctx_s {
     release_factors();
     release_workspace();
     w7.release(); mt.release(); qf.release(); px.release(); py.release(); pz.release();
-    coef128.release(); coef64.release(); wtab.release(); scratch8.release();
+    coef128.release(); coef64.release(); wtab.release(); scratch8.release(); gradw.release();
     assembled = false;
   }
 };
@@ -451,20 +452,26 @@ oras_status oras_assemble(oras_ctx c, const oras_grid* g, const double* vel_dev,
   TRY(build_coefficients(c));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->assembled = true;
+  c->weights_match_m = true;
   c->t_assemble = now() - t0;
   return ORAS_OK;
 }
 
-oras_status oras_set_m(oras_ctx c, const double* m_dev) {
+oras_status oras_set_m(oras_ctx c, const double* m_dev) { return oras_set_m_ex(c, m_dev, 0); }
+
+oras_status oras_set_m_ex(oras_ctx c, const double* m_dev, int flags) {
   if (!c) return ORAS_E_ARG;
   if (!m_dev) return fail(c, ORAS_E_ARG, "null m");
+  if (flags & ~ORAS_WEIGHTS_FOLLOW_M) return fail(c, ORAS_E_ARG, "unknown set_m flags");
   if (!c->assembled) return fail(c, ORAS_E_STATE, "set_m before assemble");
   TRY(check_device(c));
   const Table& t = weight_table();
   c->release_factors();
+  const bool follow = (flags & ORAS_WEIGHTS_FOLLOW_M) != 0;
   launch_fields(nullptr, nullptr, m_dev, c->wtab.as<double>(), t.count, t.g0, t.dg, c->nx, c->ny,
                 c->nz, c->h, c->omega, c->w7.as<double>(), c->qf.as<double2>(), c->mt.as<double2>(),
-                c->stream, 1);
+                c->stream, follow ? 0 : 1);
+  c->weights_match_m = follow;
   HIP_TRY(c, hipGetLastError());
   TRY(build_coefficients(c));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -950,13 +957,32 @@ oras_status oras_spread(oras_ctx c, const void* d_dev, int nrhs, const int* rec_
 
 oras_status oras_gradient(oras_ctx c, const void* u_dev, const void* mu_dev, int nrhs,
                           double* g_dev) {
+  return oras_gradient_ex(c, u_dev, mu_dev, nrhs, 0, g_dev);
+}
+
+oras_status oras_gradient_ex(oras_ctx c, const void* u_dev, const void* mu_dev, int nrhs,
+                             int flags, double* g_dev) {
   if (!c) return ORAS_E_ARG;
   if (!u_dev || !mu_dev || !g_dev) return fail(c, ORAS_E_ARG, "null pointer");
   if (nrhs < 1) return fail(c, ORAS_E_ARG, "nrhs must be >= 1");
+  if (flags & ~ORAS_GRAD_WEIGHTS) return fail(c, ORAS_E_ARG, "unknown gradient flags");
   if (!c->assembled) return fail(c, ORAS_E_STATE, "gradient before assemble");
+  const bool weights = (flags & ORAS_GRAD_WEIGHTS) != 0;
+  if (weights && !c->weights_match_m)
+    return fail(c, ORAS_E_STATE,
+                "weight gradient needs weights that follow m (frozen by the last set_m)");
   TRY(check_device(c));
   launch_gradient(opview(c), c->qf.as<double2>(), (const double2*)u_dev, (const double2*)mu_dev,
                   nrhs, g_dev, c->stream);
+  if (weights) {
+    const long long sc = weight_grad_scratch(c->nx, c->ny, c->nz);
+    TRY(check_free(c, (double)sc * sizeof(double) - (double)c->gradw.bytes));
+    TRY(dev_alloc(c, c->gradw, (size_t)sc * sizeof(double)));
+    const Table& t = weight_table();
+    launch_weight_gradient(opview(c), c->qf.as<double2>(), c->wtab.as<double>(), t.count, t.g0,
+                           t.dg, (const double2*)u_dev, (const double2*)mu_dev, nrhs,
+                           c->gradw.as<double>(), g_dev, c->stream);
+  }
   HIP_TRY(c, hipGetLastError());
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return ORAS_OK;

@@ -181,4 +181,12 @@ void launch_gradient(const OpView& op, const double2* qfac, const double2* u, co
 template <typename R>
 void launch_cast(const double2* src, C<R>* dst, long long count, hipStream_t st);
 
+// Stencil-weight part of the gradient (weights following m): g -= sum_k
+// dw_k/dm Re H_k.  scratch holds weight_grad_scratch(nx, ny, nz) doubles.
+long long weight_grad_scratch(int nx, int ny, int nz);
+void launch_weight_gradient(const OpView& op, const double2* qfac, const double* wtab,
+                            int tab_count, double g0, double dg, const double2* u,
+                            const double2* mu, int nrhs, double* scratch, double* g,
+                            hipStream_t st);
+
 }  // namespace oras

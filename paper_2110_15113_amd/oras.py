@@ -48,6 +48,8 @@ class Interface(ct.Structure):
 
 
 IFACE_ROBIN, IFACE_PML = 0, 1
+WEIGHTS_FOLLOW_M = 1   # set_m flag
+GRAD_WEIGHTS = 1       # gradient flag
 
 
 class SolveOpts(ct.Structure):
@@ -76,6 +78,9 @@ SIGNATURES = {
     "oras_factor_subdomains": (ct.c_int, [ct.c_void_p, ct.POINTER(ct.c_int), ct.c_int, ct.c_int]),
     "oras_factor_subdomains_ex": (ct.c_int, [ct.c_void_p, ct.POINTER(ct.c_int), ct.c_int, ct.c_int,
                                              ct.c_void_p]),
+    "oras_set_m_ex": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int]),
+    "oras_gradient_ex": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_int,
+                                    ct.c_void_p]),
     "oras_solve": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_double,
                               ct.POINTER(SolveOpts), ct.POINTER(SolveInfo)]),
     "oras_point_sources": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int,
@@ -210,9 +215,14 @@ class Solver:
         self.shape = (nz, ny, nx)
         self.prec = prec
 
-    def set_m(self, m: torch.Tensor):
+    def set_m(self, m: torch.Tensor, weights: str = "frozen"):
+        """New squared slowness.  weights: "frozen" (kept from assemble) or
+        "follow" (picked again from the local G at m)."""
         _need(m, torch.float64, self.device, self.shape, name="m")
-        self._check(lib().oras_set_m(self._ctx, _ptr(m)))
+        if weights not in ("frozen", "follow"):
+            raise ValueError("weights must be 'frozen' or 'follow'")
+        flags = WEIGHTS_FOLLOW_M if weights == "follow" else 0
+        self._check(lib().oras_set_m_ex(self._ctx, _ptr(m), flags))
 
     def factor(self, parts: Sequence[int], overlap: int = 2, prec: int = C128,
                interface: str = "robin", R0: float = 0.3, power: int = 2):
@@ -303,12 +313,15 @@ class Solver:
         self._check(lib().oras_spread(self._ctx, _ptr(d), nrhs, _ptr(r), r.shape[0], _ptr(b)))
         return b
 
-    def gradient(self, u: torch.Tensor, mu: torch.Tensor) -> torch.Tensor:
+    def gradient(self, u: torch.Tensor, mu: torch.Tensor, weights: bool = False) -> torch.Tensor:
+        """-Re sum_c mu_c^H (dA/dm) u_c; weights=True adds the stencil weights'
+        dependence on m (requires weights that follow m)."""
         nrhs = u.shape[0]
         _need(u, torch.complex128, self.device, (nrhs,) + self.shape, name="u")
         _need(mu, torch.complex128, self.device, u.shape, name="mu")
         g = torch.empty(self.shape, dtype=torch.float64, device=self.device)
-        self._check(lib().oras_gradient(self._ctx, _ptr(u), _ptr(mu), nrhs, _ptr(g)))
+        self._check(lib().oras_gradient_ex(self._ctx, _ptr(u), _ptr(mu), nrhs,
+                                           GRAD_WEIGHTS if weights else 0, _ptr(g)))
         return g
 
     # -- test hooks ----------------------------------------------------------

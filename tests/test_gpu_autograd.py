@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import adjoint, direct, operator as op
+from oracle import adjoint, direct, operator as op, stencil_table as st
 from paper_2110_15113_amd import workloads as wl
 
 from gpu_util import need_gpu, say
@@ -94,4 +94,52 @@ def test_finite_differences_random_directions():
         with torch.no_grad():
             fd = (J(m0 + eps * dm) - J(m0 - eps * dm)) / (2 * eps)
         an = (g * dm).sum()
+        assert abs(fd - an) <= 1e-5 * abs(fd), (t, float(fd), float(an))
+
+
+def test_exact_weights_gradient_matches_oracle_and_differences():
+    """weights='follow': the forward picks the stencil weights from G(m) at
+    every model (sec. 2.3) and the backward adds their table-slope term; the
+    gradient matches the oracle's exact gradient and central differences."""
+    need_gpu()
+    from paper_2110_15113_amd.autograd import receiver_data
+    w = wl.small_random((14, 12, 11), npml=2, q=50.0, nsrc=3, seed=37, parts=(2, 2, 1))
+    rec = [(4, 4, 3), (7, 5, 4), (9, 8, 6), (5, 9, 7)]
+    say("autograd exact weights")
+    rng = np.random.default_rng(8)
+    m_np = (1.0 / w.vel ** 2) * (1 + 0.05 * rng.standard_normal(w.vel.shape))
+    d_obs = (rng.normal(size=(3, len(rec))) + 1j * rng.normal(size=(3, len(rec)))) * 1e-5
+    F = adjoint.fields_from_m(m_np, w.Q, w.omega, w.h, w.npml, float(w.vel.max()))
+    A = op.assemble(F)
+    J_ref, _, U, MU = adjoint.misfit_and_gradient(F, w.sources, rec, d_obs,
+                                                  lambda b: direct.solve(A, F.shape, b))
+    g_ref = adjoint.gradient_exact(F, U, MU, m_np)
+    fs = _setup(w, rec, (2, 2, 1), 1e-12)
+    fs.weights = "follow"
+    dev = fs.solver.device
+    d_obs_t = torch.as_tensor(d_obs, device=dev)
+
+    def J(m):
+        return 0.5 * (receiver_data(m, fs) - d_obs_t).abs().pow(2).sum()
+
+    m = torch.tensor(m_np, device=dev, requires_grad=True)
+    Jv = J(m)
+    Jv.backward()
+    assert abs(Jv.item() - J_ref) <= 1e-8 * J_ref
+    g = m.grad.cpu().numpy()
+    assert np.abs(g - g_ref).max() <= 1e-6 * np.abs(g_ref).max()
+    m0 = torch.as_tensor(m_np, device=dev)
+    # the weights are piecewise linear in G: directions move only nodes whose
+    # G lies inside a table segment, away from its knots, so J is smooth along
+    # them and central differences are second-order accurate
+    G = 2 * np.pi / (w.omega * w.h * np.sqrt(m_np))
+    frac = np.modf((G - st.G_MIN) / st.G_STEP)[0]
+    smooth = torch.as_tensor(((frac > 0.1) & (frac < 0.9)).astype(np.float64), device=dev)
+    for t in range(3):
+        dm = torch.as_tensor(rng.standard_normal(w.vel.shape), device=dev)
+        dm = dm / dm.abs().max() * m0 * smooth
+        eps = 1e-4
+        with torch.no_grad():
+            fd = (J(m0 + eps * dm) - J(m0 - eps * dm)) / (2 * eps)
+        an = (m.grad * dm).sum()
         assert abs(fd - an) <= 1e-5 * abs(fd), (t, float(fd), float(an))

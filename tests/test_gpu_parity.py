@@ -134,3 +134,55 @@ def test_sources_sample_spread_gradient():
     g = S.gradient(to_dev(U, S), to_dev(MU, S)).cpu().numpy()
     ref = adjoint.gradient(F, U, MU)
     assert np.abs(g - ref).max() < 1e-11 * np.abs(ref).max()
+
+
+GRAD_CASES = [
+    dict(n=(13, 11, 12), npml=3, q=60.0, nrhs=2, seed=41),
+    dict(n=(20, 17, 9), npml=2, q=None, nrhs=3, seed=42),
+]
+
+
+@pytest.mark.parametrize("case", GRAD_CASES)
+def test_exact_gradient_matches_oracle(case):
+    """Weights following m (sec. 2.3): gradient with the table-slope term, at
+    the assembled model and after set_m(..., weights='follow') to a perturbed
+    model; the coefficients after the update match the oracle's fields."""
+    need_gpu()
+    w = wl.small_random(case["n"], npml=case["npml"], q=case["q"], seed=case["seed"])
+    say(f"exact gradient {case}")
+    S = setup(w)
+    shape = (w.nz, w.ny, w.nx)
+    U = rand_field(shape, case["nrhs"], 5)
+    MU = rand_field(shape, case["nrhs"], 6)
+    cref = float(w.vel.max())
+    m0 = 1.0 / w.vel ** 2
+    rng = np.random.default_rng(case["seed"])
+    m1 = m0 * (1 + 0.08 * rng.standard_normal(m0.shape))
+    for m, update in ((m0, False), (m1, True)):
+        if update:
+            S.set_m(to_dev(m, S), weights="follow")
+        F = adjoint.fields_from_m(m, w.Q, w.omega, w.h, w.npml, cref)
+        C = S.coefficients().cpu().numpy()
+        ref_c = op.row_coeffs(F)
+        assert np.abs(C - ref_c).max() <= 1e-11 * np.abs(ref_c).max()
+        ref = adjoint.gradient_exact(F, U, MU, m)
+        frozen = adjoint.gradient(F, U, MU)
+        g = S.gradient(to_dev(U, S), to_dev(MU, S), weights=True).cpu().numpy()
+        assert np.abs(g - ref).max() <= 1e-11 * np.abs(ref).max(), update
+        # the weight term is a sizeable part of the result
+        assert np.abs(ref - frozen).max() > 1e-3 * np.abs(ref).max()
+        g0 = S.gradient(to_dev(U, S), to_dev(MU, S)).cpu().numpy()
+        assert np.abs(g0 - frozen).max() <= 1e-11 * np.abs(frozen).max()
+
+
+def test_exact_gradient_needs_weights_that_follow_m():
+    need_gpu()
+    from paper_2110_15113_amd import oras
+    w = wl.small_random((9, 8, 7), npml=1, seed=43)
+    S = setup(w)
+    U = to_dev(rand_field((w.nz, w.ny, w.nx), 1, 1), S)
+    S.set_m(to_dev(1.01 / w.vel ** 2, S))             # frozen weights
+    with pytest.raises(oras.OrasError):
+        S.gradient(U, U, weights=True)
+    S.set_m(to_dev(1.01 / w.vel ** 2, S), weights="follow")
+    S.gradient(U, U, weights=True)
