@@ -217,6 +217,44 @@ oras_status oras_gradient(oras_ctx ctx, const void* u_dev, const void* mu_dev, i
 oras_status oras_gradient_ex(oras_ctx ctx, const void* u_dev, const void* mu_dev, int nrhs,
                              int flags, double* g_dev);
 
+/* Block low-rank (BLR) plane inverses (sec. 3: the local factors in BLR
+ * form with a threshold eps_BLR, 1e-3 in the paper's runs; Table 4).
+ *
+ * Compresses the current factors in place of the dense plane inverses for
+ * every later apply and solve (the factorisation itself is unchanged).  Each
+ * plane of a subdomain box is cut into patches of at most pmax x pmax nodes
+ * (along x ceil(sx / pmax) parts by floor split, likewise along y; patch
+ * index py * npx + px).  Diagonal patch blocks stay dense; every other block
+ * is replaced by U V from a cross approximation with complete pivoting that
+ * stops once the largest remaining entry is at most eps times the plane's
+ * largest entry (so the bound holds for every entry of the error); a block
+ * whose rank would exceed b_I b_J / (b_I + b_J) stays dense.  Pivots are
+ * chosen in the factor precision.
+ *
+ * eps in [0, 1), pmax in 2..8 (ORAS_E_ARG otherwise); needs factors
+ * (ORAS_E_STATE).  info (host, may be NULL) receives the compression
+ * statistics.  The compressed form is dropped by the next assemble, set_m or
+ * factor_subdomains.  Device memory: the compressed operands, plus a few
+ * bytes per block while compressing; the dense factors stay allocated. */
+typedef struct {
+  double eps;
+  int pmax;
+  int max_rank;             /* largest rank of a low-rank block */
+  long long blocks;         /* off-diagonal patch blocks, all planes */
+  long long lowrank;        /* of which stored as U V */
+  double mean_rank;         /* mean rank of the low-rank blocks */
+  double stored_entries;    /* complex entries of the compressed inverses */
+  double dense_entries;     /* complex entries of the dense inverses (p^2 per plane) */
+  double t_compress;        /* wall-clock seconds */
+} oras_blr_info;
+oras_status oras_compress_factors(oras_ctx ctx, double eps, int pmax, oras_blr_info* info);
+
+/* Test hook: the rank table of plane `plane` of subdomain `sub` after
+ * oras_compress_factors, npatch x npatch ints (row I, column J; -1: stored
+ * dense, which includes the diagonal) into ranks_host (capacity ints). */
+oras_status oras_blr_ranks(oras_ctx ctx, int sub, int plane, int* ranks_host, int capacity,
+                           int* npatch);
+
 /* Test hooks running the same kernels as the solver.
  * oras_apply_A: y = A x in precision prec (ORAS_C64 needs stencil_prec C64).
  * oras_apply_M: y = M^{-1} x with the current factors.
@@ -236,7 +274,10 @@ oras_status oras_profile(oras_ctx ctx, int enable);
 
 /* Accumulated plane-GEMM time (s), number of plane products, and their
  * algorithmic work: 8 p^2 nrhs flops and p^2 + 2 p nrhs (+ p nrhs backward)
- * complex entries moved per subdomain, p = plane size of its box. */
+ * complex entries moved per subdomain, p = plane size of its box.  With BLR
+ * inverses a plane product is the projection and expansion pair, and the
+ * work is that of the stored blocks: 8 nrhs flops per stored entry, the
+ * stored entries plus the gathered and written rows. */
 oras_status oras_kernel_stats(oras_ctx ctx, double* gemm_seconds, long long* gemm_launches,
                               double* gemm_flops, double* gemm_bytes);
 

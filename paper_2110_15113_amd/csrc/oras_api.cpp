@@ -83,6 +83,17 @@ struct oras_ctx_s {
   long long max_p = 0, max_box = 0, y_rows = 0, tv_rows = 0;
   double t_factor = 0;
 
+  // block low-rank plane inverses (oras_compress_factors), dropped with the factors
+  bool blr = false;
+  DevBuf blr_bsubs, blr_items, blr_addr, blr_store, blr_bt;
+  BlrApply blr_plan;
+  long long blr_bt_rows = 0;
+  std::vector<int> blr_ranks;               // per block, (sub, plane, I, J) order
+  std::vector<long long> blr_rank_off;      // first block of (sub, plane): sub * max_sz + plane
+  std::vector<int> blr_npch;
+  std::vector<double> blr_f_fwd, blr_f_bwd, blr_b_fwd, blr_b_bwd;   // per plane step
+  oras_blr_info blr_info{};
+
   // per-solve workspace (grown on demand)
   DevBuf ybuf, tvbuf, V, Z, Bint, Xint, Tmp, Tmp64, partial, small;
   long long ws_s = 0;
@@ -99,7 +110,18 @@ struct oras_ctx_s {
     release_all();
     for (hipEvent_t e : gemm_ev) (void)hipEventDestroy(e);
   }
+  void release_blr() {
+    blr_bsubs.release(); blr_items.release(); blr_addr.release(); blr_store.release();
+    blr_bt.release();
+    blr_plan = BlrApply();
+    blr_ranks.clear();
+    blr_rank_off.clear();
+    blr_npch.clear();
+    blr_bt_rows = 0;
+    blr = false;
+  }
   void release_factors() {
+    release_blr();
     subs_dev.release(); fac.release(); tbuf.release(); lca.release();
     plan = OrasPlan();
     status.release();
@@ -243,7 +265,26 @@ oras_status oras_apply_internal(oras_ctx c, const double2* v, const double* scal
     ev = c->gemm_ev.data();
   }
   const OrasPlan& pl = c->plan;
-  if (c->factor_prec == ORAS_C64) {
+  if (c->blr) {
+    const size_t cs = csize(c->factor_prec);
+    TRY(dev_alloc(c, c->blr_bt, (size_t)(c->blr_bt_rows * pad16(s)) * cs));
+    const BlrApply& bp = c->blr_plan;
+    if (c->factor_prec == ORAS_C64) {
+      if (z128)
+        launch_oras_apply_blr<float, double2>(bp, c->blr_store.as<float2>(), c->lca.as<float2>(),
+                                              c->ybuf.as<float2>(), c->blr_bt.as<float2>(), v,
+                                              scale, (double2*)z, c->nx, c->ny, s, c->stream, ev);
+      else
+        launch_oras_apply_blr<float, float2>(bp, c->blr_store.as<float2>(), c->lca.as<float2>(),
+                                             c->ybuf.as<float2>(), c->blr_bt.as<float2>(), v,
+                                             scale, (float2*)z, c->nx, c->ny, s, c->stream, ev);
+    } else {
+      launch_oras_apply_blr<double, double2>(bp, c->blr_store.as<double2>(),
+                                             c->lca.as<double2>(), c->ybuf.as<double2>(),
+                                             c->blr_bt.as<double2>(), v, scale, (double2*)z,
+                                             c->nx, c->ny, s, c->stream, ev);
+    }
+  } else if (c->factor_prec == ORAS_C64) {
     if (z128)
       launch_oras_apply<float, double2>(pl, c->fac.as<float2>(), c->lca.as<float2>(),
                                         c->ybuf.as<float2>(), c->tvbuf.as<float2>(), v, scale,
@@ -268,12 +309,20 @@ oras_status oras_apply_internal(oras_ctx c, const double2* v, const double* scal
       HIP_TRY(c, hipEventElapsedTime(&ms, ev[2 * st], ev[2 * st + 1]));
       const bool bwd = st >= c->max_sz;
       const int k = bwd ? (c->max_sz - 2 - (st - c->max_sz)) : st;
+      c->gemm_s += ms * 1e-3;
+      c->gemm_launches += 1;
+      if (c->blr) {
+        // stored entries: 8 nrhs flops each; bytes: stored entries, gathered
+        // rows and written rows (per right-hand side)
+        c->gemm_flops += 8.0 * (bwd ? c->blr_f_bwd[k] : c->blr_f_fwd[k]) * nrhs;
+        c->gemm_bytes += cs * ((bwd ? c->blr_f_bwd[k] : c->blr_f_fwd[k]) +
+                               (bwd ? c->blr_b_bwd[k] : c->blr_b_fwd[k]) * nrhs);
+        continue;
+      }
       const double p2 = bwd ? c->plane_p2_bwd[k] : c->plane_p2_fwd[k];
       const double p1 = bwd ? c->plane_p_bwd[k] : c->plane_p_fwd[k];
-      c->gemm_s += ms * 1e-3;
       c->gemm_flops += 8.0 * p2 * nrhs;
       c->gemm_bytes += cs * (p2 + (bwd ? 3.0 : 2.0) * p1 * nrhs);
-      c->gemm_launches += 1;
     }
   }
   return ORAS_OK;
@@ -301,6 +350,39 @@ oras_status check_receivers(oras_ctx c, const int* rec_dev, int nrec) {
 }  // namespace
 
 // ------------------------------------------------------------------ C ABI --
+namespace {
+
+// Patch extents along one axis: n nodes in ceil(n / pmax) parts by floor split.
+std::vector<int> patch_cuts(int n, int pmax) {
+  const int parts = (n + pmax - 1) / pmax;
+  std::vector<int> c(parts + 1);
+  for (int t = 0; t <= parts; ++t) c[t] = (int)((long long)t * n / parts);
+  return c;
+}
+
+struct TmpBufs {
+  DevBuf smax, blocks, ranks, err;
+  ~TmpBufs() { smax.release(); blocks.release(); ranks.release(); err.release(); }
+};
+
+// Items of one plane ordered so that item i runs on XCD i % 8 and every
+// subdomain's items share an XCD (padding items have sub = -1).
+void interleave(const std::vector<BlrItem>& in, std::vector<BlrItem>& out, int& first, int& count) {
+  std::vector<std::vector<BlrItem>> bucket(8);
+  for (const BlrItem& it : in) bucket[it.sub % 8].push_back(it);
+  size_t longest = 0;
+  for (auto& b : bucket) longest = std::max(longest, b.size());
+  first = (int)out.size();
+  BlrItem pad;
+  std::memset(&pad, 0, sizeof(pad));
+  pad.sub = -1;
+  for (size_t i = 0; i < longest; ++i)
+    for (int x = 0; x < 8; ++x) out.push_back(i < bucket[x].size() ? bucket[x][i] : pad);
+  count = (int)(out.size() - first);
+}
+
+}  // namespace
+
 extern "C" {
 
 oras_status oras_create(oras_ctx* out, int device, void* hip_stream) {
@@ -640,6 +722,295 @@ oras_status oras_factor_subdomains_ex(oras_ctx c, const int parts[3], int overla
   c->plan.max_nt = max_nt;
   c->plan.max_p = max_p;
   c->factored = true;
+  return ORAS_OK;
+}
+
+oras_status oras_compress_factors(oras_ctx c, double eps, int pmax, oras_blr_info* info) {
+  if (!c) return ORAS_E_ARG;
+  if (!(eps >= 0.0 && eps < 1.0)) return fail(c, ORAS_E_ARG, "eps must lie in [0, 1)");
+  if (pmax < 2 || pmax > BLR_PMAX) return fail(c, ORAS_E_ARG, "pmax must be 2..8");
+  if (!c->factored) return fail(c, ORAS_E_STATE, "compress_factors before factor_subdomains");
+  TRY(check_device(c));
+  c->release_blr();
+  const double t0 = now();
+  const int nsub = (int)c->subs.size(), max_sz = c->max_sz;
+  const size_t cs = csize(c->factor_prec);
+  std::vector<BlrSub> bsubs(nsub);
+  std::vector<std::vector<int>> cx(nsub), cy(nsub);
+  std::vector<int> npch(nsub);
+  std::vector<long long> rank_off((size_t)nsub * max_sz, -1);
+  long long nblocks = 0;
+  for (int j = 0; j < nsub; ++j) {
+    const SubDesc& d = c->subs[j];
+    cx[j] = patch_cuts(d.sx, pmax);
+    cy[j] = patch_cuts(d.sy, pmax);
+    bsubs[j].npx = (int)cx[j].size() - 1;
+    bsubs[j].npy = (int)cy[j].size() - 1;
+    bsubs[j].bt_off = 0;
+    npch[j] = bsubs[j].npx * bsubs[j].npy;
+    for (int k = 0; k < d.sz; ++k) {
+      rank_off[(size_t)j * max_sz + k] = nblocks;
+      nblocks += (long long)npch[j] * npch[j];
+    }
+  }
+  if (nblocks >= (1LL << 31)) return fail(c, ORAS_E_ARG, "too many patch blocks");
+  std::vector<BlrBlock> blocks((size_t)nblocks);
+  for (int j = 0; j < nsub; ++j)
+    for (int k = 0; k < c->subs[j].sz; ++k) {
+      long long b = rank_off[(size_t)j * max_sz + k];
+      for (int I = 0; I < npch[j]; ++I)
+        for (int J = 0; J < npch[j]; ++J, ++b) {
+          BlrBlock& x = blocks[(size_t)b];
+          std::memset(&x, 0, sizeof(x));
+          x.sub = j;
+          x.k = k;
+          x.I = I;
+          x.J = J;
+          x.rank = -1;
+          x.p_off = -1;
+        }
+    }
+  // pass 1: ranks
+  TmpBufs tmp;
+  TRY(check_free(c, (double)nblocks * (sizeof(BlrBlock) + sizeof(int)) + 8.0 * nsub * max_sz));
+  TRY(dev_alloc(c, tmp.smax, (size_t)nsub * max_sz * sizeof(double)));
+  TRY(dev_alloc(c, tmp.blocks, (size_t)nblocks * sizeof(BlrBlock)));
+  TRY(dev_alloc(c, tmp.ranks, (size_t)nblocks * sizeof(int)));
+  TRY(dev_alloc(c, tmp.err, sizeof(int)));
+  TRY(dev_alloc(c, c->blr_bsubs, (size_t)nsub * sizeof(BlrSub)));
+  HIP_TRY(c, hipMemcpyAsync(c->blr_bsubs.p, bsubs.data(), (size_t)nsub * sizeof(BlrSub),
+                            hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(tmp.blocks.p, blocks.data(), (size_t)nblocks * sizeof(BlrBlock),
+                            hipMemcpyHostToDevice, c->stream));
+  const SubDesc* sdev = c->subs_dev.as<SubDesc>();
+  if (c->factor_prec == ORAS_C64) {
+    launch_blr_plane_max<float>(sdev, nsub, max_sz, c->fac.as<float2>(), tmp.smax.as<double>(),
+                                c->stream);
+    launch_blr_compress<float>(sdev, c->blr_bsubs.as<BlrSub>(), tmp.blocks.as<BlrBlock>(), nblocks,
+                               c->fac.as<float2>(), tmp.smax.as<double>(), max_sz, eps,
+                               tmp.ranks.as<int>(), nullptr, nullptr, c->stream);
+  } else {
+    launch_blr_plane_max<double>(sdev, nsub, max_sz, c->fac.as<double2>(), tmp.smax.as<double>(),
+                                 c->stream);
+    launch_blr_compress<double>(sdev, c->blr_bsubs.as<BlrSub>(), tmp.blocks.as<BlrBlock>(),
+                                nblocks, c->fac.as<double2>(), tmp.smax.as<double>(), max_sz, eps,
+                                tmp.ranks.as<int>(), nullptr, nullptr, c->stream);
+  }
+  HIP_TRY(c, hipGetLastError());
+  std::vector<int> ranks((size_t)nblocks);
+  HIP_TRY(c, hipMemcpyAsync(ranks.data(), tmp.ranks.p, (size_t)nblocks * sizeof(int),
+                            hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+
+  // layout of the compressed operands, work items and address lists
+  std::vector<std::vector<BlrItem>> pit(max_sz), eit(max_sz);
+  std::vector<int> addr;
+  long long store = 0;
+  std::vector<long long> tcap(nsub, 0);
+  std::vector<double> f_fwd(max_sz, 0.0), f_bwd(max_sz, 0.0), b_fwd(max_sz, 0.0),
+      b_bwd(max_sz, 0.0);
+  oras_blr_info inf{};
+  inf.eps = eps;
+  inf.pmax = pmax;
+  double rank_sum = 0;
+  for (int j = 0; j < nsub; ++j) {
+    const SubDesc& d = c->subs[j];
+    const int np = npch[j], npx = bsubs[j].npx;
+    std::vector<int> bsz(np), origin(np), width(np);
+    for (int I = 0; I < np; ++I) {
+      const int px = I % npx, py = I / npx;
+      width[I] = cx[j][px + 1] - cx[j][px];
+      bsz[I] = width[I] * (cy[j][py + 1] - cy[j][py]);
+      origin[I] = cy[j][py] * d.sx + cx[j][px];
+    }
+    auto node = [&](int I, int l) { return origin[I] + (l / width[I]) * d.sx + l % width[I]; };
+    for (int k = 0; k < d.sz; ++k) {
+      const long long base = rank_off[(size_t)j * max_sz + k];
+      auto rk = [&](int I, int J) { return ranks[(size_t)(base + (long long)I * np + J)]; };
+      const bool act_bwd = k <= d.sz - 2 && k >= d.olo[2] - d.lo[2];
+      double fl = 0, by = 0;
+      // projection operands: V of the low-rank blocks of column patch J, stacked by I
+      std::vector<int> RJ(np, 0), tb(np, 0), poff_row((size_t)np * np, 0);
+      std::vector<long long> poff(np, -1);
+      std::vector<int> pmp(np, 0);
+      int trow = 0;
+      for (int J = 0; J < np; ++J) {
+        for (int I = 0; I < np; ++I)
+          if (I != J && rk(I, J) >= 0) {
+            poff_row[(size_t)I * np + J] = RJ[J];
+            RJ[J] += rk(I, J);
+          }
+        tb[J] = trow;
+        trow += RJ[J];
+        if (RJ[J] == 0) continue;
+        const int mp = (RJ[J] + 31) / 32 * 32, kp = (bsz[J] + 3) / 4 * 4;
+        poff[J] = store;
+        pmp[J] = mp;
+        for (int rt = 0; rt < mp / 32; ++rt) {
+          BlrItem it;
+          std::memset(&it, 0, sizeof(it));
+          it.sub = j;
+          it.patch = J;
+          it.rows = std::min(32, RJ[J] - 32 * rt);
+          it.mpad = mp;
+          it.K = kp;
+          it.row0 = 32 * rt;
+          it.out_row = d.p + tb[J] + 32 * rt;
+          it.a_off = store;
+          it.addr_off = -1;
+          pit[k].push_back(it);
+        }
+        store += (long long)mp * kp;
+        fl += (double)RJ[J] * bsz[J];
+        by += bsz[J] + RJ[J];
+      }
+      tcap[j] = std::max(tcap[j], (long long)trow);
+      // expansion operands: [S_II | S_IJ dense | U_IJ low-rank] of row patch I
+      for (int I = 0; I < np; ++I) {
+        const long long aoff = (long long)addr.size();
+        int K = 0;
+        std::vector<int> koff(np, 0);
+        for (int J = -1; J < np; ++J) {
+          const int JJ = J < 0 ? I : J;          // the diagonal block first
+          if (J == I) continue;
+          koff[JJ] = K;
+          const int r = JJ == I ? -1 : rk(I, JJ);
+          if (r < 0) {
+            for (int l = 0; l < bsz[JJ]; ++l) addr.push_back(node(JJ, l));
+            K += bsz[JJ];
+          } else {
+            for (int q = 0; q < r; ++q)
+              addr.push_back(d.p + tb[JJ] + poff_row[(size_t)I * np + JJ] + q);
+            K += r;
+          }
+        }
+        const int kp = (K + 3) / 4 * 4;
+        for (int q = K; q < kp; ++q) addr.push_back(0);
+        BlrItem it;
+        std::memset(&it, 0, sizeof(it));
+        it.sub = j;
+        it.patch = I;
+        it.rows = bsz[I];
+        it.mpad = 64;
+        it.K = kp;
+        it.row0 = 0;
+        it.out_row = 0;
+        it.a_off = store;
+        it.addr_off = aoff;
+        eit[k].push_back(it);
+        for (int J = 0; J < np; ++J) {
+          BlrBlock& x = blocks[(size_t)(base + (long long)I * np + J)];
+          x.rank = J == I ? -1 : rk(I, J);
+          x.e_off = store;
+          x.e_koff = koff[J];
+          if (J != I && x.rank >= 0) {
+            x.p_off = poff[J];
+            x.p_mpad = pmp[J];
+            x.p_row = poff_row[(size_t)I * np + J];
+            inf.lowrank += 1;
+            rank_sum += x.rank;
+            inf.max_rank = std::max(inf.max_rank, x.rank);
+          }
+          if (J != I) inf.blocks += 1;
+        }
+        store += 64LL * kp;
+        fl += (double)bsz[I] * K;
+        by += K + (act_bwd ? 2.0 : 1.0) * bsz[I];
+      }
+      f_fwd[k] += fl;
+      b_fwd[k] += by;
+      if (act_bwd) {
+        f_bwd[k] += fl;
+        b_bwd[k] += by;
+      }
+      inf.stored_entries += fl;
+      inf.dense_entries += (double)d.p * d.p;
+    }
+  }
+  inf.mean_rank = inf.lowrank ? rank_sum / inf.lowrank : 0.0;
+  long long bt_rows = 0;
+  for (int j = 0; j < nsub; ++j) {
+    bsubs[j].bt_off = bt_rows;
+    bt_rows += c->subs[j].p + tcap[j];
+  }
+  std::vector<BlrItem> items;
+  BlrApply& pl = c->blr_plan;
+  pl.p_first.assign(max_sz, 0);
+  pl.p_count.assign(max_sz, 0);
+  pl.e_first.assign(max_sz, 0);
+  pl.e_count.assign(max_sz, 0);
+  for (int k = 0; k < max_sz; ++k) {
+    interleave(pit[k], items, pl.p_first[k], pl.p_count[k]);
+    interleave(eit[k], items, pl.e_first[k], pl.e_count[k]);
+  }
+  // pass 2: write the operands
+  TRY(check_free(c, (double)store * cs + (double)items.size() * sizeof(BlrItem) +
+                        (double)addr.size() * sizeof(int)));
+  TRY(dev_alloc(c, c->blr_store, (size_t)std::max(store, 1LL) * cs));
+  TRY(dev_alloc(c, c->blr_items, std::max<size_t>(items.size(), 1) * sizeof(BlrItem)));
+  TRY(dev_alloc(c, c->blr_addr, std::max<size_t>(addr.size(), 1) * sizeof(int)));
+  launch_zero(c->blr_store.p, (size_t)store * cs, c->stream);
+  launch_zero(tmp.err.p, sizeof(int), c->stream);
+  HIP_TRY(c, hipMemcpyAsync(c->blr_bsubs.p, bsubs.data(), (size_t)nsub * sizeof(BlrSub),
+                            hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(tmp.blocks.p, blocks.data(), (size_t)nblocks * sizeof(BlrBlock),
+                            hipMemcpyHostToDevice, c->stream));
+  if (!items.empty())
+    HIP_TRY(c, hipMemcpyAsync(c->blr_items.p, items.data(), items.size() * sizeof(BlrItem),
+                              hipMemcpyHostToDevice, c->stream));
+  if (!addr.empty())
+    HIP_TRY(c, hipMemcpyAsync(c->blr_addr.p, addr.data(), addr.size() * sizeof(int),
+                              hipMemcpyHostToDevice, c->stream));
+  if (c->factor_prec == ORAS_C64)
+    launch_blr_compress<float>(sdev, c->blr_bsubs.as<BlrSub>(), tmp.blocks.as<BlrBlock>(), nblocks,
+                               c->fac.as<float2>(), tmp.smax.as<double>(), max_sz, eps, nullptr,
+                               c->blr_store.as<float2>(), tmp.err.as<int>(), c->stream);
+  else
+    launch_blr_compress<double>(sdev, c->blr_bsubs.as<BlrSub>(), tmp.blocks.as<BlrBlock>(),
+                                nblocks, c->fac.as<double2>(), tmp.smax.as<double>(), max_sz, eps,
+                                nullptr, c->blr_store.as<double2>(), tmp.err.as<int>(), c->stream);
+  HIP_TRY(c, hipGetLastError());
+  int err = 0;
+  HIP_TRY(c, hipMemcpyAsync(&err, tmp.err.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (err) {
+    c->release_blr();
+    return fail(c, ORAS_E_NUMERIC, "BLR compression did not reproduce its ranks");
+  }
+  pl.subs = sdev;
+  pl.bsubs = c->blr_bsubs.as<BlrSub>();
+  pl.items = c->blr_items.as<BlrItem>();
+  pl.addr = c->blr_addr.as<int>();
+  pl.nsub = nsub;
+  pl.max_sz = max_sz;
+  pl.max_p = c->max_p;
+  c->blr_bt_rows = bt_rows;
+  c->blr_ranks.swap(ranks);
+  c->blr_rank_off.swap(rank_off);
+  c->blr_npch.swap(npch);
+  c->blr_f_fwd = f_fwd;
+  c->blr_f_bwd = f_bwd;
+  c->blr_b_fwd = b_fwd;
+  c->blr_b_bwd = b_bwd;
+  inf.t_compress = now() - t0;
+  c->blr_info = inf;
+  c->blr = true;
+  if (info) *info = inf;
+  return ORAS_OK;
+}
+
+oras_status oras_blr_ranks(oras_ctx c, int sub, int plane, int* ranks_host, int capacity,
+                           int* npatch) {
+  if (!c) return ORAS_E_ARG;
+  if (!c->blr) return fail(c, ORAS_E_STATE, "no compressed factors");
+  if (sub < 0 || sub >= (int)c->subs.size()) return fail(c, ORAS_E_ARG, "sub out of range");
+  if (plane < 0 || plane >= c->subs[sub].sz) return fail(c, ORAS_E_ARG, "plane out of range");
+  const int np = c->blr_npch[sub];
+  if (npatch) *npatch = np;
+  if (!ranks_host) return ORAS_OK;
+  if (capacity < np * np) return fail(c, ORAS_E_ARG, "capacity below npatch^2");
+  const long long base = c->blr_rank_off[(size_t)sub * c->max_sz + plane];
+  for (int q = 0; q < np * np; ++q) ranks_host[q] = c->blr_ranks[(size_t)(base + q)];
   return ORAS_OK;
 }
 

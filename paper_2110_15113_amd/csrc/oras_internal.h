@@ -181,6 +181,62 @@ void launch_gradient(const OpView& op, const double2* qfac, const double2* u, co
 template <typename R>
 void launch_cast(const double2* src, C<R>* dst, long long count, hipStream_t st);
 
+// ------------------------------------------------- block low-rank inverses --
+// Patch grid of one subdomain plane (rectangles of at most pmax x pmax nodes)
+// and the rows of its operand buffer (t rows 0..p-1, then projection rows).
+struct BlrSub {
+  long long bt_off;      // first operand-buffer row of the subdomain
+  int npx, npy;
+};
+// One patch block (I, J) of one plane inverse: where compression writes it.
+struct BlrBlock {
+  int sub, k, I, J;
+  int rank;              // planned rank (-1: stored dense)
+  int e_koff;            // first K column of the block in the expansion operand of patch I
+  int p_mpad;            // row stride of the projection operand of patch J
+  int p_row;             // first row of the block's V in that operand
+  long long e_off;       // complex offset of the expansion operand of patch I
+  long long p_off;       // complex offset of the projection operand of patch J (-1: none)
+};
+// One wave's work in a gather GEMM: rows of the output of one patch.
+struct BlrItem {
+  int sub;               // -1: padding (no work)
+  int patch;
+  int rows;              // valid output rows
+  int mpad;              // row stride of the operand storage ([k / 4][row][k % 4])
+  int K;                 // operand columns, a multiple of 4
+  int row0;              // first operand row of this item
+  int out_row;           // projection: operand-buffer row (from bt_off) of output row 0
+  int pad_;
+  long long a_off;       // complex offset of the operand storage
+  long long addr_off;    // expansion: offset of the K operand-buffer rows in the address list
+};
+struct BlrApply {
+  const SubDesc* subs;
+  const BlrSub* bsubs;
+  const BlrItem* items;
+  const int* addr;
+  int nsub, max_sz;
+  long long max_p;
+  // per plane k: [first, count) of the projection and expansion items
+  std::vector<int> p_first, p_count, e_first, e_count;
+};
+constexpr int BLR_PMAX = 8;     // largest patch edge (64-node patches)
+
+template <typename R>
+void launch_blr_plane_max(const SubDesc* subs, int nsub, int max_sz, const C<R>* fac,
+                          double* smax, hipStream_t st);
+// rank_out (pass without astore) or the compressed operands (pass with astore;
+// err[0] is set when a block's rank differs from the planned one)
+template <typename R>
+void launch_blr_compress(const SubDesc* subs, const BlrSub* bsubs, const BlrBlock* blocks,
+                         long long nblocks, const C<R>* fac, const double* smax, int max_sz,
+                         double eps, int* rank_out, C<R>* astore, int* err, hipStream_t st);
+template <typename R, typename Z>
+void launch_oras_apply_blr(const BlrApply& pl, const C<R>* astore, const C<R>* lca, C<R>* ybuf,
+                           C<R>* bt, const double2* v, const double* scale, Z* z, int nx, int ny,
+                           int s, hipStream_t st, hipEvent_t* gemm_ev = nullptr);
+
 // Stencil-weight part of the gradient (weights following m): g -= sum_k
 // dw_k/dm Re H_k.  scratch holds weight_grad_scratch(nx, ny, nz) doubles.
 long long weight_grad_scratch(int nx, int ny, int nz);

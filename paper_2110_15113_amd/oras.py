@@ -66,6 +66,13 @@ class SolveInfo(ct.Structure):
 
 _LIB = None
 
+class BlrInfo(ct.Structure):
+    _fields_ = [("eps", ct.c_double), ("pmax", ct.c_int), ("max_rank", ct.c_int),
+                ("blocks", ct.c_longlong), ("lowrank", ct.c_longlong), ("mean_rank", ct.c_double),
+                ("stored_entries", ct.c_double), ("dense_entries", ct.c_double),
+                ("t_compress", ct.c_double)]
+
+
 SIGNATURES = {
     "oras_create": (ct.c_int, [ct.POINTER(ct.c_void_p), ct.c_int, ct.c_void_p]),
     "oras_destroy": (None, [ct.c_void_p]),
@@ -99,6 +106,10 @@ SIGNATURES = {
                                      ct.POINTER(ct.c_double)]),
     "oras_coefficients": (ct.c_int, [ct.c_void_p, ct.c_void_p]),
     "oras_subdomain": (ct.c_int, [ct.c_void_p, ct.c_int, ct.POINTER(ct.c_int),
+                                  ct.POINTER(ct.c_int)]),
+    "oras_compress_factors": (ct.c_int, [ct.c_void_p, ct.c_double, ct.c_int,
+                                         ct.POINTER(BlrInfo)]),
+    "oras_blr_ranks": (ct.c_int, [ct.c_void_p, ct.c_int, ct.c_int, ct.c_void_p, ct.c_int,
                                   ct.POINTER(ct.c_int)]),
 }
 
@@ -340,6 +351,22 @@ class Solver:
     def coefficients(self) -> torch.Tensor:
         out = torch.empty((27,) + self.shape, dtype=torch.complex128, device=self.device)
         self._check(lib().oras_coefficients(self._ctx, _ptr(out)))
+        return out
+
+    def compress(self, eps: float = 1e-3, pmax: int = 8) -> dict:
+        """Block low-rank plane inverses (threshold eps, patches of at most
+        pmax x pmax nodes) for every later apply and solve."""
+        info = BlrInfo()
+        self._check(lib().oras_compress_factors(self._ctx, float(eps), int(pmax), ct.byref(info)))
+        return {f: getattr(info, f) for f, _ in BlrInfo._fields_}
+
+    def blr_ranks(self, sub: int, plane: int) -> np.ndarray:
+        """Rank table (npatch, npatch) of one plane inverse; -1 = dense."""
+        n = ct.c_int()
+        self._check(lib().oras_blr_ranks(self._ctx, sub, plane, None, 0, ct.byref(n)))
+        out = np.zeros((n.value, n.value), dtype=np.int32)
+        self._check(lib().oras_blr_ranks(self._ctx, sub, plane, out.ctypes.data_as(ct.c_void_p),
+                                         out.size, None))
         return out
 
     def subdomains(self):

@@ -23,7 +23,7 @@ def test_library_exports_every_declared_symbol():
     L = oras.lib()
     hdr = open(os.path.join(ROOT, "include", "oras.h")).read()
     names = set(re.findall(r"\b(oras_[a-z_A-Z]+)\s*\(", hdr))
-    assert len(names) >= 18
+    assert len(names) >= 20
     for name in names:
         assert hasattr(L, name), name
     assert names <= set(oras.SIGNATURES), names - set(oras.SIGNATURES)
@@ -91,6 +91,14 @@ def test_host_only_context_validates_before_device():
         assert L.oras_gradient(ctx, fake, fake, 1, fake) == 2
         idx = (ct.c_int * 3)(1, 2, 3)
         assert L.oras_point_sources(ctx, idx, None, 1, fake) == 2
+        # BLR compression: arguments first, then the missing factors
+        assert L.oras_compress_factors(ctx, -1e-3, 8, None) == 1
+        assert L.oras_compress_factors(ctx, 1.0, 8, None) == 1
+        assert L.oras_compress_factors(ctx, float("nan"), 8, None) == 1
+        assert L.oras_compress_factors(ctx, 1e-3, 1, None) == 1
+        assert L.oras_compress_factors(ctx, 1e-3, 9, None) == 1
+        assert L.oras_compress_factors(ctx, 1e-3, 8, None) == 2
+        assert L.oras_blr_ranks(ctx, 0, 0, None, 0, None) == 2
     finally:
         L.oras_destroy(ctx)
     assert L.oras_create(None, 0, None) == 1

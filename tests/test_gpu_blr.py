@@ -1,0 +1,110 @@
+"""Block low-rank plane inverses (sec. 3: BLR local factors with threshold
+eps_BLR; Table 4) on the GPU against the oracle's BLR local solves."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import blr as oblr, direct, operator as op, oras as ooras
+from paper_2110_15113_amd import workloads as wl
+
+from gpu_util import need_gpu, oracle_fields, rand_field, rel, say, setup, to_dev
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    dict(n=(18, 16, 14), parts=(2, 2, 1), ov=2, npml=2, q=60.0, pmax=4, nrhs=3),
+    dict(n=(23, 21, 12), parts=(1, 1, 2), ov=2, npml=2, q=None, pmax=8, nrhs=9),
+    dict(n=(16, 19, 15), parts=(2, 1, 2), ov=1, npml=2, q=80.0, pmax=5, nrhs=37),
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("eps", [1e-3, 1e-5])
+def test_blr_fp64_ranks_and_apply_match_oracle(case, eps):
+    need_gpu()
+    w = wl.small_random(case["n"], npml=case["npml"], q=case["q"], seed=9,
+                        parts=case["parts"], overlap=case["ov"])
+    say(f"blr fp64 {case} eps={eps}")
+    F = oracle_fields(w)
+    M = oblr.OrasBLR(F, case["parts"], case["ov"], eps, case["pmax"])
+    S = setup(w, prec=2, parts=case["parts"], overlap=case["ov"])
+    info = S.compress(eps, case["pmax"])
+    assert info["lowrank"] > 0
+    mismatch = total = 0
+    for j, sol in enumerate(M.solvers):
+        for k, plane in enumerate(sol.inv):
+            got = S.blr_ranks(j, k)
+            mismatch += int(np.sum(got != plane.rank))
+            total += got.size
+    assert mismatch == 0, (mismatch, total)
+    x = rand_field((w.nz, w.ny, w.nx), case["nrhs"], 3)
+    ref = M.apply(x)
+    got = S.apply_M(to_dev(x, S)).cpu().numpy()
+    assert rel(got, ref) < 1e-9, rel(got, ref)
+
+
+def test_blr_eps_zero_is_the_dense_apply():
+    need_gpu()
+    c = CASES[1]
+    w = wl.small_random(c["n"], npml=c["npml"], q=c["q"], seed=9, parts=c["parts"],
+                        overlap=c["ov"])
+    say("blr eps 0")
+    x = rand_field((w.nz, w.ny, w.nx), 5, 4)
+    S = setup(w, prec=2, parts=c["parts"], overlap=c["ov"])
+    dense = S.apply_M(to_dev(x, S)).cpu().numpy()
+    S.compress(0.0, 8)
+    got = S.apply_M(to_dev(x, S)).cpu().numpy()
+    assert rel(got, dense) < 1e-12, rel(got, dense)
+    # a new factorisation drops the compressed form
+    S.factor(c["parts"], c["ov"], 2)
+    again = S.apply_M(to_dev(x, S)).cpu().numpy()
+    assert rel(again, dense) < 1e-14
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_blr_fp32_apply_matches_oracle(case):
+    need_gpu()
+    w = wl.small_random(case["n"], npml=case["npml"], q=case["q"], seed=9,
+                        parts=case["parts"], overlap=case["ov"])
+    say(f"blr fp32 {case}")
+    F = oracle_fields(w)
+    eps = 1e-3
+    M = oblr.OrasBLR(F, case["parts"], case["ov"], eps, case["pmax"])
+    Md = ooras.ORAS(F, case["parts"], case["ov"])
+    S = setup(w, prec=1, parts=case["parts"], overlap=case["ov"])
+    S.compress(eps, case["pmax"])
+    x = rand_field((w.nz, w.ny, w.nx), case["nrhs"], 5)
+    ref = M.apply(x)
+    got = S.apply_M(to_dev(x, S)).cpu().numpy()
+    assert rel(got, ref) < 1e-3, rel(got, ref)
+    # the compression error itself: BLR against the exact local solves
+    assert rel(got, Md.apply(x)) < 50 * eps, rel(got, Md.apply(x))
+    agree = total = 0
+    for j, sol in enumerate(M.solvers):
+        for k, plane in enumerate(sol.inv):
+            got_r = S.blr_ranks(j, k)
+            agree += int(np.sum(np.abs(got_r - plane.rank) <= 1))
+            total += got_r.size
+    assert agree >= 0.95 * total, (agree, total)
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_blr_solve_config1(prec):
+    need_gpu()
+    w = wl.config1()
+    say(f"blr solve config1 prec={prec}")
+    F = oracle_fields(w)
+    b = op.point_sources(F, w.sources)
+    u = direct.solve(op.assemble(F), F.shape, b)
+    its = {}
+    for blr in (False, True):
+        S = setup(w, prec=prec, parts=w.parts, overlap=w.overlap)
+        if blr:
+            S.compress(1e-3, 8)
+        tol = 1e-6 if prec == 1 else 1e-8
+        r = S.solve(to_dev(b, S), tol, restart=w.restart)
+        assert bool(r.converged.all())
+        x = r.x.cpu().numpy()
+        assert rel(x, u) < (1e-4 if prec == 1 else 1e-6), rel(x, u)
+        its[blr] = int(r.iters.max())
+    assert its[True] <= its[False] + 5, its
