@@ -11,19 +11,22 @@
 // product costs as much as the block) stays dense, as do diagonal blocks.
 //
 // One plane step of the apply, for all subdomains:
-//   * the right-hand side t is written row-major into rows 0..p-1 of the
-//     subdomain's part of the operand buffer;
+//   * the right-hand side t is written into the subdomain's part of the
+//     operand buffer in patch-major order (each patch's rows consecutive,
+//     padded with zero rows to a multiple of 8);
 //   * projection: for every column patch J, T_J = V_J t_J (V_J: the V of the
-//     patch's low-rank blocks, stacked) into further rows of that buffer;
+//     patch's low-rank blocks, stacked), each row stored with the rows that
+//     its row patch I needs (T_I = [T_IJ for the low-rank J], consecutive);
 //   * expansion: for every row patch I,
-//         y_I = [S_II | S_IJ (dense blocks) | U_IJ (low-rank)] [t_I; t_J; T_IJ],
-//     whose K operand rows are gathered through an address list; the
+//         y_I = [S_II | S_IJ (dense blocks) | U_IJ (low-rank)] [t_I; t_J; T_I],
+//     whose operand rows form a few runs of consecutive buffer rows; the
 //     epilogue stores the plane rows and, on final planes, the owned nodes
 //     (the same restricted prolongation as the dense substitution).
-// Both are gather GEMMs on MFMA with the stored operand in [k / 4][row][k % 4]
-// order.  Compression runs twice: a first pass finds the ranks, the host lays
-// out the operands, and a second pass (the same deterministic kernel) writes
-// them.
+// Both are GEMMs on MFMA with the stored operand in [k / 4][row][k % 4]
+// order and affine operand rows inside each run, so loads do not wait on
+// other loads.  Compression runs twice: a first pass finds the ranks, the
+// host lays out the operands, and a second pass (the same deterministic
+// kernel) writes them.
 #include <algorithm>
 #include <climits>
 
@@ -240,36 +243,45 @@ compress_kernel(const SubDesc* __restrict__ subs, const BlrSub* __restrict__ bsu
 }
 
 // ------------------------------------------------------ right-hand side --
-// t rows of every subdomain (row-major, pad16(s) columns): forward
-// scale * v - L_k y_{k-1}, backward U_k x_{k+1}.
-template <typename R>
-__global__ void blr_rhs_kernel(const SubDesc* __restrict__ subs, const BlrSub* __restrict__ bsubs,
-                               int k, int bwd, const C<R>* __restrict__ lca,
-                               const C<R>* __restrict__ ybuf, C<R>* __restrict__ bt,
-                               const double2* __restrict__ v, const double* __restrict__ scale,
-                               int nx, int ny, int s, int s16) {
-  const SubDesc sd = subs[blockIdx.y];
-  if (!plane_active(sd, k, bwd)) return;
-  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long long)sd.p * s) return;
-  const int q = (int)(idx / s), c = (int)(idx % s);
-  const int qx = q % sd.sx, qy = q / sd.sx;
+// Operand-buffer row (from bt_off) of plane node (qx, qy): its patch's first
+// t row plus its index inside the patch.  The patch along x is the part t
+// with floor(t sx / npx) <= qx < floor((t+1) sx / npx), i.e.
+// t = floor(((qx + 1) npx - 1) / sx); likewise along y.
+__device__ inline int t_row(const SubDesc& sd, const BlrSub& bs, const int* __restrict__ lists,
+                            int qx, int qy) {
+  const int px = ((qx + 1) * bs.npx - 1) / sd.sx, py = ((qy + 1) * bs.npy - 1) / sd.sy;
+  const int x0 = px * sd.sx / bs.npx, x1 = (px + 1) * sd.sx / bs.npx;
+  const int y0 = py * sd.sy / bs.npy;
+  return lists[bs.ptab + py * bs.npx + px] + (qy - y0) * (x1 - x0) + (qx - x0);
+}
+
+// Right-hand side entry t[q][c]: forward scale * v - L_k y_{k-1}, backward
+// U_k x_{k+1} (couplings leaving the box are exact zeros in the local
+// coefficients, so clamped neighbour indices contribute nothing).
+template <typename R, int NC>
+__device__ inline void rhs_entries(const SubDesc& sd, int k, int bwd, int qx, int qy, int c,
+                                   const C<R>* __restrict__ lca, const C<R>* __restrict__ ybuf,
+                                   const double2* __restrict__ v, const double* __restrict__ scale,
+                                   int nx, int ny, int s, C<R>* t) {
   using T = C<R>;
-  T t = mk<R>(0, 0);
+#pragma unroll
+  for (int j = 0; j < NC; ++j) t[j] = mk<R>(0, 0);
   if (!bwd) {
     const long long g = ((long long)(sd.lo[2] + k) * ny + sd.lo[1] + qy) * nx + sd.lo[0] + qx;
-    const double2 vv = v[g * s + c];
-    const double sc = scale ? scale[c] : 1.0;
-    t.x = (R)(vv.x * sc);
-    t.y = (R)(vv.y * sc);
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      const double2 vv = v[g * s + c + j];
+      const double sc = scale ? scale[c + j] : 1.0;
+      t[j].x = (R)(vv.x * sc);
+      t[j].y = (R)(vv.y * sc);
+    }
   }
   if (bwd || k > 0) {
     const long long nbox = (long long)sd.sx * sd.sy * sd.sz;
     const long long node = ((long long)k * sd.sy + qy) * sd.sx + qx;
     const T* L = lca + sd.lca_off;
-    const T* Yn = ybuf + (sd.y_off + (long long)(bwd ? k + 1 : k - 1) * sd.P) * s;
+    const T* Yn = ybuf + (sd.y_off + (long long)(bwd ? k + 1 : k - 1) * sd.P) * s + c;
     const int ez = bwd ? 1 : -1;
-    // couplings leaving the box are exact zeros in the local coefficients
 #pragma unroll
     for (int dy = -1; dy <= 1; ++dy) {
       const int py = min(max(qy + dy, 0), sd.sy - 1);
@@ -277,16 +289,60 @@ __global__ void blr_rhs_kernel(const SubDesc* __restrict__ subs, const BlrSub* _
       for (int dx = -1; dx <= 1; ++dx) {
         const int px = min(max(qx + dx, 0), sd.sx - 1);
         const T l = L[eidx(dx, dy, ez) * nbox + node];
-        const T y = Yn[(long long)(py * sd.sx + px) * s + c];
-        if (bwd) cfma(t, l, y);
-        else cfms(t, l, y);
+        const T* yr = Yn + (long long)(py * sd.sx + px) * s;
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+          if (bwd) cfma(t[j], l, yr[j]);
+          else cfms(t[j], l, yr[j]);
+        }
       }
     }
   }
-  bt[(bsubs[blockIdx.y].bt_off + q) * s16 + c] = t;
 }
 
-// --------------------------------------------------------- gather GEMMs --
+// FP32: sixteen lanes per plane row, two columns each (whole cache lines per
+// load, one coefficient broadcast per row), one 16-byte store per lane.
+constexpr int RB_ROWS = 16;
+__global__ void __launch_bounds__(RB_ROWS * 16)
+blr_rhs_f32_kernel(const SubDesc* __restrict__ subs, const BlrSub* __restrict__ bsubs,
+                   const int* __restrict__ lists, int nrb, int k, int bwd,
+                   const float2* __restrict__ lca, const float2* __restrict__ ybuf,
+                   float2* __restrict__ bt, const double2* __restrict__ v,
+                   const double* __restrict__ scale, int nx, int ny, int s, int s16) {
+  const SubDesc sd = subs[blockIdx.y];
+  if (!plane_active(sd, k, bwd)) return;
+  const int rb = blockIdx.x % nrb, cc = blockIdx.x / nrb;
+  const int q = rb * RB_ROWS + (threadIdx.x >> 4);
+  const int c = 32 * cc + 2 * (threadIdx.x & 15);
+  if (q >= sd.p || c >= s) return;                 // s is even
+  const int qx = q % sd.sx, qy = q / sd.sx;
+  float2 t[2];
+  rhs_entries<float, 2>(sd, k, bwd, qx, qy, c, lca, ybuf, v, scale, nx, ny, s, t);
+  const BlrSub bs = bsubs[blockIdx.y];
+  *reinterpret_cast<float4*>(bt + (bs.bt_off + t_row(sd, bs, lists, qx, qy)) * s16 + c) =
+      make_float4(t[0].x, t[0].y, t[1].x, t[1].y);
+}
+
+// FP64: one thread per entry.
+__global__ void blr_rhs_f64_kernel(const SubDesc* __restrict__ subs,
+                                   const BlrSub* __restrict__ bsubs, const int* __restrict__ lists,
+                                   int k, int bwd, const double2* __restrict__ lca,
+                                   const double2* __restrict__ ybuf, double2* __restrict__ bt,
+                                   const double2* __restrict__ v, const double* __restrict__ scale,
+                                   int nx, int ny, int s, int s16) {
+  const SubDesc sd = subs[blockIdx.y];
+  if (!plane_active(sd, k, bwd)) return;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)sd.p * s) return;
+  const int q = (int)(idx / s), c = (int)(idx % s);
+  const int qx = q % sd.sx, qy = q / sd.sx;
+  double2 t[1];
+  rhs_entries<double, 1>(sd, k, bwd, qx, qy, c, lca, ybuf, v, scale, nx, ny, s, t);
+  const BlrSub bs = bsubs[blockIdx.y];
+  bt[(bs.bt_off + t_row(sd, bs, lists, qx, qy)) * s16 + c] = t[0];
+}
+
+// --------------------------------------------------------- segment GEMMs --
 // Work-group id -> (item, column group), with the items ordered so that every
 // subdomain's items sit on one XCD.
 __device__ inline bool item_map(int nitems, int ncg, int& it, int& cg) {
@@ -296,25 +352,15 @@ __device__ inline bool item_map(int nitems, int ncg, int& it, int& cg) {
   return it < nitems;
 }
 
-// Operand-buffer row of the item's k-th operand row.  Projection: node k of
-// the patch, as an offset from the patch's first node (its first node beyond
-// the patch, where the stored operand column is zero); expansion: from the
-// address list.
-template <int MODE>
-__device__ inline int b_row(const BlrItem& item, const int* addr, int w, int bsz, int sx, int kap) {
-  if (MODE == 0) {
-    const int l = kap < bsz ? kap : 0;
-    return (l / w) * sx + l % w;
-  }
-  return addr[item.addr_off + kap];
-}
-
 // Complex FP32: 32x32x2 MFMA, RT tiles of 32 rows x 32 columns per wave.
+// Operand row kk of the item is operand-buffer row rbase + (kk - 4 kq) for the
+// 4-row group kq; projection items read the patch's t rows, expansion items
+// walk their segments.
 template <int RT, int MODE, typename Z>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
 blr_gemm_f32_kernel(const SubDesc* __restrict__ subs, const BlrSub* __restrict__ bsubs,
                     const BlrItem* __restrict__ items, int nitems, int ncg, int k, int bwd,
-                    const float2* __restrict__ astore, const int* __restrict__ addr,
+                    const float2* __restrict__ astore, const int* __restrict__ lists,
                     float2* __restrict__ bt, float2* __restrict__ ybuf, Z* __restrict__ z,
                     int nx, int ny, int s, int s16) {
   using ZR = typename std::conditional<sizeof(Z) == 8, float, double>::type;
@@ -325,21 +371,16 @@ blr_gemm_f32_kernel(const SubDesc* __restrict__ subs, const BlrSub* __restrict__
   const SubDesc sd = subs[item.sub];
   if (!plane_active(sd, k, bwd)) return;
   const BlrSub bs = bsubs[item.sub];
-  int x0, w, y0, hh;
-  patch_box(sd.sx, sd.sy, bs.npx, bs.npy, item.patch, x0, w, y0, hh);
-  const int bsz = w * hh;
-  const int origin = y0 * sd.sx + x0;           // plane row of the patch's first node
   const float* btf = reinterpret_cast<const float*>(bt + bs.bt_off * s16);
   const float4* A = reinterpret_cast<const float4*>(astore + item.a_off);
   const int lane = threadIdx.x, rr = lane & 31, h = lane >> 5;
   const bool odd = (rr & 1) != 0;
   const int c0 = 32 * cg;
+  // columns at or beyond s16 read column s16 - 1 (in bounds; their results are dropped)
   int colf[2];
-  bool colok[2];
 #pragma unroll
   for (int nb = 0; nb < 2; ++nb) {
-    const int col = c0 + 16 * nb + (rr >> 1);
-    colok[nb] = col < s16;
+    const int col = min(c0 + 16 * nb + (rr >> 1), s16 - 1);
     colf[nb] = 2 * col + (rr & 1);
   }
   f32x16 acc[RT][2][2];
@@ -352,26 +393,18 @@ blr_gemm_f32_kernel(const SubDesc* __restrict__ subs, const BlrSub* __restrict__
         acc[rt][nb][0][j] = 0.f;
         acc[rt][nb][1][j] = 0.f;
       }
-  const int nkq = item.K >> 2;
-#pragma unroll 2
-  for (int kq = 0; kq < nkq; ++kq) {
-    int row[2];
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const int kap = 4 * kq + 2 * h + e;
-      row[e] = MODE == 0 ? origin + b_row<0>(item, addr, w, bsz, sd.sx, kap)
-                         : b_row<1>(item, addr, w, bsz, sd.sx, kap);
-    }
-    float bv[2][2];
+  // one 4-row group: lane h takes operand rows 4 kq + 2 h + e, e = 0, 1
+  auto load = [&](int kq, int rbase, float (&bv)[2][2], float4 (&a)[RT]) {
 #pragma unroll
     for (int e = 0; e < 2; ++e)
 #pragma unroll
       for (int nb = 0; nb < 2; ++nb)
-        bv[e][nb] = colok[nb] ? btf[(long long)row[e] * 2 * s16 + colf[nb]] : 0.f;
-    float4 a[RT];
+        bv[e][nb] = btf[(long long)(rbase + 2 * h + e) * 2 * s16 + colf[nb]];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
       a[rt] = A[((long long)kq * item.mpad + item.row0 + 32 * rt + rr) * 2 + h];
+  };
+  auto mma = [&](const float (&bv)[2][2], const float4 (&a)[RT]) {
 #pragma unroll
     for (int e = 0; e < 2; ++e)
 #pragma unroll
@@ -387,27 +420,94 @@ blr_gemm_f32_kernel(const SubDesc* __restrict__ subs, const BlrSub* __restrict__
           acc[rt][nb][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, b2, acc[rt][nb][1], 0, 0, 0);
         }
       }
+  };
+  // groups q0..q1-1 (a positive, even count: runs are whole multiples of 8
+  // rows) with operand rows from rbase0 on; two groups in flight in two
+  // register sets.  Nothing in the loop is conditional (loads past the end
+  // repeat the last group), so every path into it has the same loads
+  // outstanding and each multiply waits only for its own group.
+  auto run = [&](int q0, int q1, int rbase0) {
+    float b0[2][2], b1[2][2];
+    float4 a0[RT], a1[RT];
+    auto ld = [&](int kq, float (&bv)[2][2], float4 (&a)[RT]) {
+      const int g = min(kq, q1 - 1);
+      load(g, rbase0 + 4 * (g - q0), bv, a);
+    };
+    // the scheduling barriers keep each group's loads where they are issued
+    // (left to itself the scheduler sinks them to their first use)
+    ld(q0, b0, a0);
+    ld(q0 + 1, b1, a1);
+    __builtin_amdgcn_sched_barrier(0);
+    for (int kq = q0; kq < q1; kq += 2) {
+      mma(b0, a0);
+      __builtin_amdgcn_sched_barrier(0);
+      ld(kq + 2, b0, a0);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(b1, a1);
+      __builtin_amdgcn_sched_barrier(0);
+      ld(kq + 3, b1, a1);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  };
+  if (MODE == 0) {
+    run(0, item.K >> 2, item.brow);
+  } else {
+    for (int sg = 0; sg < item.nseg; ++sg) {
+      const int4 seg = *reinterpret_cast<const int4*>(lists + item.list_off + 4 * sg);
+      run(seg.x >> 2, (seg.x + seg.z) >> 2, seg.y);
+    }
   }
   // accumulator item i of lane l: row 8 (i / 4) + 4 (l / 32) + i % 4, real column l % 32
   if (MODE == 0) {
-    float* Tf = reinterpret_cast<float*>(bt + (bs.bt_off + item.out_row) * s16);
+    // destination rows first (all loads in flight together), then the stores
+    int dest[RT][16];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        dest[rt][i] = lists[item.list_off + 32 * rt + 8 * (i / 4) + 4 * h + (i % 4)];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
         const int lr = 32 * rt + 8 * (i / 4) + 4 * h + (i % 4);
         if (lr >= item.rows) continue;
+        float* Tf = reinterpret_cast<float*>(bt + (bs.bt_off + dest[rt][i]) * s16);
 #pragma unroll
         for (int nb = 0; nb < 2; ++nb) {
           const int col = c0 + 16 * nb + (rr >> 1);
           if (col >= s) continue;
-          Tf[(long long)lr * 2 * s16 + colf[nb]] = acc[rt][nb][0][i] + acc[rt][nb][1][i];
+          Tf[2 * col + (rr & 1)] = acc[rt][nb][0][i] + acc[rt][nb][1][i];
         }
       }
     return;
   }
+  int x0, w, y0, hh;
+  patch_box(sd.sx, sd.sy, bs.npx, bs.npy, item.patch, x0, w, y0, hh);
+  const int bsz = w * hh;
   const bool final_plane = bwd || (k == sd.sz - 1);
   float* Yk = reinterpret_cast<float*>(ybuf + (sd.y_off + (long long)k * sd.P) * s);
+  // backward: x_k = y_k - (...): read every old value first (all loads in
+  // flight together), then write
+  float old[RT][16][2];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) old[rt][i][nb] = 0.f;
+  if (bwd) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int l = min(32 * rt + 8 * (i / 4) + 4 * h + (i % 4), bsz - 1);
+        const float* yr = Yk + (long long)((y0 + l / w) * sd.sx + x0 + l % w) * 2 * s;
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+          old[rt][i][nb] = yr[2 * min(c0 + 16 * nb + (rr >> 1), s - 1) + (rr & 1)];
+      }
+  }
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -429,7 +529,7 @@ blr_gemm_f32_kernel(const SubDesc* __restrict__ subs, const BlrSub* __restrict__
         if (col >= s) continue;
         const int fi = 2 * col + (rr & 1);
         float val = acc[rt][nb][0][i] + acc[rt][nb][1][i];
-        if (bwd) val = yr[fi] - val;
+        if (bwd) val = old[rt][i][nb] - val;
         yr[fi] = val;
         if (zoff >= 0) reinterpret_cast<ZR*>(z + zoff)[fi] = (ZR)val;
       }
@@ -443,7 +543,7 @@ template <int RG, int MODE>
 __global__ void __launch_bounds__(64)
 blr_gemm_f64_kernel(const SubDesc* __restrict__ subs, const BlrSub* __restrict__ bsubs,
                     const BlrItem* __restrict__ items, int nitems, int ncg, int k, int bwd,
-                    const double2* __restrict__ astore, const int* __restrict__ addr,
+                    const double2* __restrict__ astore, const int* __restrict__ lists,
                     double2* __restrict__ bt, double2* __restrict__ ybuf,
                     double2* __restrict__ z, int nx, int ny, int s, int s16) {
   int it, cg;
@@ -453,10 +553,6 @@ blr_gemm_f64_kernel(const SubDesc* __restrict__ subs, const BlrSub* __restrict__
   const SubDesc sd = subs[item.sub];
   if (!plane_active(sd, k, bwd)) return;
   const BlrSub bs = bsubs[item.sub];
-  int x0, w, y0, hh;
-  patch_box(sd.sx, sd.sy, bs.npx, bs.npy, item.patch, x0, w, y0, hh);
-  const int bsz = w * hh;
-  const int origin = y0 * sd.sx + x0;
   const double2* btc = bt + bs.bt_off * s16;
   const double2* A = astore + item.a_off;
   const int lane = threadIdx.x, m = lane & 15, kk = lane >> 4;
@@ -468,15 +564,12 @@ blr_gemm_f64_kernel(const SubDesc* __restrict__ subs, const BlrSub* __restrict__
   for (int rg = 0; rg < RG; ++rg)
 #pragma unroll
     for (int ns = 0; ns < 2; ++ns) acc[rg][ns] = f64x4{0, 0, 0, 0};
-  const int nkq = item.K >> 2;
-  for (int kq = 0; kq < nkq; ++kq) {
-    const int kap = 4 * kq + kk;
-    const int row = MODE == 0 ? origin + b_row<0>(item, addr, w, bsz, sd.sx, kap)
-                              : b_row<1>(item, addr, w, bsz, sd.sx, kap);
+  auto group = [&](int kq, int rbase) {
+    const long long row = rbase + kk;
 #pragma unroll
     for (int ns = 0; ns < 2; ++ns) {
       const int col = c0 + 8 * ns + bn;
-      const double2 bv = col < s16 ? btc[(long long)row * s16 + col] : make_double2(0.0, 0.0);
+      const double2 bv = col < s16 ? btc[row * s16 + col] : make_double2(0.0, 0.0);
       const double b1 = im ? bv.y : bv.x;
       const double b2 = im ? bv.x : -bv.y;
 #pragma unroll
@@ -486,24 +579,37 @@ blr_gemm_f64_kernel(const SubDesc* __restrict__ subs, const BlrSub* __restrict__
         acc[rg][ns] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b2, acc[rg][ns], 0, 0, 0);
       }
     }
+  };
+  if (MODE == 0) {
+    const int nkq = item.K >> 2;
+    for (int kq = 0; kq < nkq; ++kq) group(kq, item.brow + 4 * kq);
+  } else {
+    for (int sg = 0; sg < item.nseg; ++sg) {
+      const int4 seg = *reinterpret_cast<const int4*>(lists + item.list_off + 4 * sg);
+      const int q0 = seg.x >> 2, q1 = (seg.x + seg.z) >> 2;
+      for (int kq = q0; kq < q1; ++kq) group(kq, seg.y + 4 * (kq - q0));
+    }
   }
   if (MODE == 0) {
-    double* Tf = reinterpret_cast<double*>(bt + (bs.bt_off + item.out_row) * s16);
 #pragma unroll
     for (int rg = 0; rg < RG; ++rg)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int lr = 16 * rg + kk + 4 * t;
         if (lr >= item.rows) continue;
+        double* Tf = reinterpret_cast<double*>(bt + (bs.bt_off + lists[item.list_off + lr]) * s16);
 #pragma unroll
         for (int ns = 0; ns < 2; ++ns) {
           const int col = c0 + 8 * ns + bn;
           if (col >= s) continue;
-          Tf[(long long)lr * 2 * s16 + 2 * col + (im ? 1 : 0)] = acc[rg][ns][t];
+          Tf[2 * col + (im ? 1 : 0)] = acc[rg][ns][t];
         }
       }
     return;
   }
+  int x0, w, y0, hh;
+  patch_box(sd.sx, sd.sy, bs.npx, bs.npy, item.patch, x0, w, y0, hh);
+  const int bsz = w * hh;
   const bool final_plane = bwd || (k == sd.sz - 1);
   double* Yk = reinterpret_cast<double*>(ybuf + (sd.y_off + (long long)k * sd.P) * s);
 #pragma unroll
@@ -536,29 +642,47 @@ blr_gemm_f64_kernel(const SubDesc* __restrict__ subs, const BlrSub* __restrict__
 
 template <typename R, typename Z> struct BlrStep;
 template <typename Z> struct BlrStep<float, Z> {
-  static void gemm(const BlrApply& pl, int k, int bwd, const float2* astore, float2* bt,
-                   float2* ybuf, Z* z, int nx, int ny, int s, int s16, hipStream_t st) {
+  static void run(const BlrApply& pl, int k, int bwd, const float2* astore, const float2* lca,
+                  float2* bt, float2* ybuf, const double2* v, const double* scale, Z* z, int nx,
+                  int ny, int s, int s16, hipStream_t st, hipEvent_t* ev) {
+    const int nrb = (int)((pl.max_p + RB_ROWS - 1) / RB_ROWS);
+    const int ncc = (s + 31) / 32;
+    hipLaunchKernelGGL(blr_rhs_f32_kernel, dim3((unsigned)(nrb * ncc), (unsigned)pl.nsub),
+                       dim3(RB_ROWS * 16), 0, st, pl.subs, pl.bsubs, pl.lists, nrb, k, bwd, lca,
+                       ybuf, bt, v, scale, nx, ny, s, s16);
+    if (ev) (void)hipEventRecord(ev[0], st);
     const int ncg = (s + 31) / 32;
     if (pl.p_count[k] > 0)
       hipLaunchKernelGGL((blr_gemm_f32_kernel<1, 0, Z>), dim3((unsigned)(pl.p_count[k] * ncg)),
                          dim3(64), 0, st, pl.subs, pl.bsubs, pl.items + pl.p_first[k],
-                         pl.p_count[k], ncg, k, bwd, astore, pl.addr, bt, ybuf, z, nx, ny, s, s16);
+                         pl.p_count[k], ncg, k, bwd, astore, pl.lists, bt, ybuf, z, nx, ny, s,
+                         s16);
     hipLaunchKernelGGL((blr_gemm_f32_kernel<2, 1, Z>), dim3((unsigned)(pl.e_count[k] * ncg)),
                        dim3(64), 0, st, pl.subs, pl.bsubs, pl.items + pl.e_first[k],
-                       pl.e_count[k], ncg, k, bwd, astore, pl.addr, bt, ybuf, z, nx, ny, s, s16);
+                       pl.e_count[k], ncg, k, bwd, astore, pl.lists, bt, ybuf, z, nx, ny, s, s16);
+    if (ev) (void)hipEventRecord(ev[1], st);
   }
 };
 template <> struct BlrStep<double, double2> {
-  static void gemm(const BlrApply& pl, int k, int bwd, const double2* astore, double2* bt,
-                   double2* ybuf, double2* z, int nx, int ny, int s, int s16, hipStream_t st) {
+  static void run(const BlrApply& pl, int k, int bwd, const double2* astore, const double2* lca,
+                  double2* bt, double2* ybuf, const double2* v, const double* scale, double2* z,
+                  int nx, int ny, int s, int s16, hipStream_t st, hipEvent_t* ev) {
+    const int bs = 256;
+    hipLaunchKernelGGL(blr_rhs_f64_kernel,
+                       dim3((unsigned)((pl.max_p * s + bs - 1) / bs), (unsigned)pl.nsub), dim3(bs),
+                       0, st, pl.subs, pl.bsubs, pl.lists, k, bwd, lca, ybuf, bt, v, scale, nx, ny,
+                       s, s16);
+    if (ev) (void)hipEventRecord(ev[0], st);
     const int ncg = (s + 15) / 16;
     if (pl.p_count[k] > 0)
       hipLaunchKernelGGL((blr_gemm_f64_kernel<2, 0>), dim3((unsigned)(pl.p_count[k] * ncg)),
                          dim3(64), 0, st, pl.subs, pl.bsubs, pl.items + pl.p_first[k],
-                         pl.p_count[k], ncg, k, bwd, astore, pl.addr, bt, ybuf, z, nx, ny, s, s16);
+                         pl.p_count[k], ncg, k, bwd, astore, pl.lists, bt, ybuf, z, nx, ny, s,
+                         s16);
     hipLaunchKernelGGL((blr_gemm_f64_kernel<4, 1>), dim3((unsigned)(pl.e_count[k] * ncg)),
                        dim3(64), 0, st, pl.subs, pl.bsubs, pl.items + pl.e_first[k],
-                       pl.e_count[k], ncg, k, bwd, astore, pl.addr, bt, ybuf, z, nx, ny, s, s16);
+                       pl.e_count[k], ncg, k, bwd, astore, pl.lists, bt, ybuf, z, nx, ny, s, s16);
+    if (ev) (void)hipEventRecord(ev[1], st);
   }
 };
 
@@ -590,16 +714,11 @@ void launch_oras_apply_blr(const BlrApply& pl, const C<R>* astore, const C<R>* l
                            int s, hipStream_t st, hipEvent_t* gemm_ev) {
   const int s16 = (int)pad16(s);
   const int nsteps = 2 * pl.max_sz - 1;
-  const int bs = 256;
-  const dim3 grhs((unsigned)((pl.max_p * s + bs - 1) / bs), (unsigned)pl.nsub);
   for (int step = 0; step < nsteps; ++step) {
     const int bwd = step >= pl.max_sz ? 1 : 0;
     const int k = bwd ? 2 * pl.max_sz - 2 - step : step;
-    hipLaunchKernelGGL((blr_rhs_kernel<R>), grhs, dim3(bs), 0, st, pl.subs, pl.bsubs, k, bwd, lca,
-                       ybuf, bt, v, scale, nx, ny, s, s16);
-    if (gemm_ev) (void)hipEventRecord(gemm_ev[2 * step], st);
-    BlrStep<R, Z>::gemm(pl, k, bwd, astore, bt, ybuf, z, nx, ny, s, s16, st);
-    if (gemm_ev) (void)hipEventRecord(gemm_ev[2 * step + 1], st);
+    BlrStep<R, Z>::run(pl, k, bwd, astore, lca, bt, ybuf, v, scale, z, nx, ny, s, s16, st,
+                       gemm_ev ? gemm_ev + 2 * step : nullptr);
   }
 }
 

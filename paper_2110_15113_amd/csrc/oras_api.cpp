@@ -85,7 +85,7 @@ struct oras_ctx_s {
 
   // block low-rank plane inverses (oras_compress_factors), dropped with the factors
   bool blr = false;
-  DevBuf blr_bsubs, blr_items, blr_addr, blr_store, blr_bt;
+  DevBuf blr_bsubs, blr_items, blr_lists, blr_store, blr_bt;
   BlrApply blr_plan;
   long long blr_bt_rows = 0;
   std::vector<int> blr_ranks;               // per block, (sub, plane, I, J) order
@@ -111,7 +111,7 @@ struct oras_ctx_s {
     for (hipEvent_t e : gemm_ev) (void)hipEventDestroy(e);
   }
   void release_blr() {
-    blr_bsubs.release(); blr_items.release(); blr_addr.release(); blr_store.release();
+    blr_bsubs.release(); blr_items.release(); blr_lists.release(); blr_store.release();
     blr_bt.release();
     blr_plan = BlrApply();
     blr_ranks.clear();
@@ -267,7 +267,12 @@ oras_status oras_apply_internal(oras_ctx c, const double2* v, const double* scal
   const OrasPlan& pl = c->plan;
   if (c->blr) {
     const size_t cs = csize(c->factor_prec);
-    TRY(dev_alloc(c, c->blr_bt, (size_t)(c->blr_bt_rows * pad16(s)) * cs));
+    // padding rows of the operand buffer must hold finite values (zero)
+    const size_t bt_bytes = (size_t)(c->blr_bt_rows * pad16(s)) * cs;
+    if (c->blr_bt.bytes < bt_bytes || !c->blr_bt.p) {
+      TRY(dev_alloc(c, c->blr_bt, bt_bytes));
+      launch_zero(c->blr_bt.p, c->blr_bt.bytes, c->stream);
+    }
     const BlrApply& bp = c->blr_plan;
     if (c->factor_prec == ORAS_C64) {
       if (z128)
@@ -802,101 +807,127 @@ oras_status oras_compress_factors(oras_ctx c, double eps, int pmax, oras_blr_inf
                             hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
 
-  // layout of the compressed operands, work items and address lists
+  // layout: per subdomain the t rows (patch-major, each patch padded to a
+  // multiple of 8 rows), then per plane the T rows of every row patch I
+  // (T_I = [T_IJ for the low-rank blocks, J ascending], padded likewise)
   std::vector<std::vector<BlrItem>> pit(max_sz), eit(max_sz);
-  std::vector<int> addr;
+  std::vector<int> lists;
   long long store = 0;
-  std::vector<long long> tcap(nsub, 0);
+  std::vector<long long> tcap(nsub, 0), trows(nsub, 0);
   std::vector<double> f_fwd(max_sz, 0.0), f_bwd(max_sz, 0.0), b_fwd(max_sz, 0.0),
       b_bwd(max_sz, 0.0);
   oras_blr_info inf{};
   inf.eps = eps;
   inf.pmax = pmax;
   double rank_sum = 0;
+  // runs of operand rows come in whole pairs of 4-row groups (multiples of 8)
+  auto pad8 = [](int v) { return (v + 7) / 8 * 8; };
   for (int j = 0; j < nsub; ++j) {
     const SubDesc& d = c->subs[j];
     const int np = npch[j], npx = bsubs[j].npx;
-    std::vector<int> bsz(np), origin(np), width(np);
+    std::vector<int> bsz(np), toff(np);
+    bsubs[j].ptab = (int)lists.size();
+    int tt = 0;
     for (int I = 0; I < np; ++I) {
       const int px = I % npx, py = I / npx;
-      width[I] = cx[j][px + 1] - cx[j][px];
-      bsz[I] = width[I] * (cy[j][py + 1] - cy[j][py]);
-      origin[I] = cy[j][py] * d.sx + cx[j][px];
+      bsz[I] = (cx[j][px + 1] - cx[j][px]) * (cy[j][py + 1] - cy[j][py]);
+      toff[I] = tt;
+      lists.push_back(tt);
+      tt += pad8(bsz[I]);
     }
-    auto node = [&](int I, int l) { return origin[I] + (l / width[I]) * d.sx + l % width[I]; };
+    trows[j] = tt;
     for (int k = 0; k < d.sz; ++k) {
       const long long base = rank_off[(size_t)j * max_sz + k];
       auto rk = [&](int I, int J) { return ranks[(size_t)(base + (long long)I * np + J)]; };
       const bool act_bwd = k <= d.sz - 2 && k >= d.olo[2] - d.lo[2];
       double fl = 0, by = 0;
+      // T rows of every row patch
+      std::vector<int> RI(np, 0), toffT(np, 0), offIJ((size_t)np * np, 0);
+      int trow = tt;
+      for (int I = 0; I < np; ++I) {
+        for (int J = 0; J < np; ++J)
+          if (J != I && rk(I, J) >= 0) {
+            offIJ[(size_t)I * np + J] = RI[I];
+            RI[I] += rk(I, J);
+          }
+        toffT[I] = trow;
+        trow += pad8(RI[I]);
+      }
+      tcap[j] = std::max(tcap[j], (long long)(trow - tt));
       // projection operands: V of the low-rank blocks of column patch J, stacked by I
-      std::vector<int> RJ(np, 0), tb(np, 0), poff_row((size_t)np * np, 0);
+      std::vector<int> prow((size_t)np * np, 0), pmp(np, 0);
       std::vector<long long> poff(np, -1);
-      std::vector<int> pmp(np, 0);
-      int trow = 0;
       for (int J = 0; J < np; ++J) {
+        int RJ = 0;
         for (int I = 0; I < np; ++I)
           if (I != J && rk(I, J) >= 0) {
-            poff_row[(size_t)I * np + J] = RJ[J];
-            RJ[J] += rk(I, J);
+            prow[(size_t)I * np + J] = RJ;
+            RJ += rk(I, J);
           }
-        tb[J] = trow;
-        trow += RJ[J];
-        if (RJ[J] == 0) continue;
-        const int mp = (RJ[J] + 31) / 32 * 32, kp = (bsz[J] + 3) / 4 * 4;
+        if (RJ == 0) continue;
+        const int mp = (RJ + 31) / 32 * 32, kp = pad8(bsz[J]);
         poff[J] = store;
         pmp[J] = mp;
+        std::vector<int> dest(mp, 0);
+        for (int I = 0; I < np; ++I)
+          if (I != J && rk(I, J) >= 0)
+            for (int q = 0; q < rk(I, J); ++q)
+              dest[prow[(size_t)I * np + J] + q] = toffT[I] + offIJ[(size_t)I * np + J] + q;
         for (int rt = 0; rt < mp / 32; ++rt) {
           BlrItem it;
           std::memset(&it, 0, sizeof(it));
           it.sub = j;
           it.patch = J;
-          it.rows = std::min(32, RJ[J] - 32 * rt);
+          it.rows = std::min(32, RJ - 32 * rt);
           it.mpad = mp;
           it.K = kp;
           it.row0 = 32 * rt;
-          it.out_row = d.p + tb[J] + 32 * rt;
+          it.brow = toff[J];
           it.a_off = store;
-          it.addr_off = -1;
+          it.list_off = (long long)lists.size();
+          lists.insert(lists.end(), dest.begin() + 32 * rt, dest.begin() + 32 * rt + 32);
           pit[k].push_back(it);
         }
         store += (long long)mp * kp;
-        fl += (double)RJ[J] * bsz[J];
-        by += bsz[J] + RJ[J];
+        fl += (double)RJ * bsz[J];
+        by += bsz[J] + RJ;
       }
-      tcap[j] = std::max(tcap[j], (long long)trow);
       // expansion operands: [S_II | S_IJ dense | U_IJ low-rank] of row patch I
       for (int I = 0; I < np; ++I) {
-        const long long aoff = (long long)addr.size();
-        int K = 0;
+        while (lists.size() % 4) lists.push_back(0);     // int4 segments
+        const long long loff = (long long)lists.size();
         std::vector<int> koff(np, 0);
-        for (int J = -1; J < np; ++J) {
-          const int JJ = J < 0 ? I : J;          // the diagonal block first
-          if (J == I) continue;
-          koff[JJ] = K;
-          const int r = JJ == I ? -1 : rk(I, JJ);
-          if (r < 0) {
-            for (int l = 0; l < bsz[JJ]; ++l) addr.push_back(node(JJ, l));
-            K += bsz[JJ];
-          } else {
-            for (int q = 0; q < r; ++q)
-              addr.push_back(d.p + tb[JJ] + poff_row[(size_t)I * np + JJ] + q);
-            K += r;
+        int K = 0, nseg = 0, kd = 0;
+        auto seg = [&](int row, int len) {
+          lists.push_back(K);
+          lists.push_back(row);
+          lists.push_back(len);
+          lists.push_back(0);
+          K += len;
+          ++nseg;
+        };
+        seg(toff[I], pad8(bsz[I]));
+        kd += bsz[I];
+        for (int J = 0; J < np; ++J)
+          if (J != I && rk(I, J) < 0) {
+            koff[J] = K;
+            seg(toff[J], pad8(bsz[J]));
+            kd += bsz[J];
           }
-        }
-        const int kp = (K + 3) / 4 * 4;
-        for (int q = K; q < kp; ++q) addr.push_back(0);
+        const int kT = K;
+        if (RI[I] > 0) seg(toffT[I], pad8(RI[I]));
+        for (int J = 0; J < np; ++J)
+          if (J != I && rk(I, J) >= 0) koff[J] = kT + offIJ[(size_t)I * np + J];
         BlrItem it;
         std::memset(&it, 0, sizeof(it));
         it.sub = j;
         it.patch = I;
         it.rows = bsz[I];
         it.mpad = 64;
-        it.K = kp;
-        it.row0 = 0;
-        it.out_row = 0;
+        it.K = K;
+        it.nseg = nseg;
         it.a_off = store;
-        it.addr_off = aoff;
+        it.list_off = loff;
         eit[k].push_back(it);
         for (int J = 0; J < np; ++J) {
           BlrBlock& x = blocks[(size_t)(base + (long long)I * np + J)];
@@ -906,16 +937,16 @@ oras_status oras_compress_factors(oras_ctx c, double eps, int pmax, oras_blr_inf
           if (J != I && x.rank >= 0) {
             x.p_off = poff[J];
             x.p_mpad = pmp[J];
-            x.p_row = poff_row[(size_t)I * np + J];
+            x.p_row = prow[(size_t)I * np + J];
             inf.lowrank += 1;
             rank_sum += x.rank;
             inf.max_rank = std::max(inf.max_rank, x.rank);
           }
           if (J != I) inf.blocks += 1;
         }
-        store += 64LL * kp;
-        fl += (double)bsz[I] * K;
-        by += K + (act_bwd ? 2.0 : 1.0) * bsz[I];
+        store += 64LL * K;
+        fl += (double)bsz[I] * (kd + RI[I]);
+        by += kd + RI[I] + (act_bwd ? 2.0 : 1.0) * bsz[I];
       }
       f_fwd[k] += fl;
       b_fwd[k] += by;
@@ -931,7 +962,7 @@ oras_status oras_compress_factors(oras_ctx c, double eps, int pmax, oras_blr_inf
   long long bt_rows = 0;
   for (int j = 0; j < nsub; ++j) {
     bsubs[j].bt_off = bt_rows;
-    bt_rows += c->subs[j].p + tcap[j];
+    bt_rows += trows[j] + tcap[j];
   }
   std::vector<BlrItem> items;
   BlrApply& pl = c->blr_plan;
@@ -945,10 +976,10 @@ oras_status oras_compress_factors(oras_ctx c, double eps, int pmax, oras_blr_inf
   }
   // pass 2: write the operands
   TRY(check_free(c, (double)store * cs + (double)items.size() * sizeof(BlrItem) +
-                        (double)addr.size() * sizeof(int)));
+                        (double)lists.size() * sizeof(int)));
   TRY(dev_alloc(c, c->blr_store, (size_t)std::max(store, 1LL) * cs));
   TRY(dev_alloc(c, c->blr_items, std::max<size_t>(items.size(), 1) * sizeof(BlrItem)));
-  TRY(dev_alloc(c, c->blr_addr, std::max<size_t>(addr.size(), 1) * sizeof(int)));
+  TRY(dev_alloc(c, c->blr_lists, std::max<size_t>(lists.size(), 1) * sizeof(int)));
   launch_zero(c->blr_store.p, (size_t)store * cs, c->stream);
   launch_zero(tmp.err.p, sizeof(int), c->stream);
   HIP_TRY(c, hipMemcpyAsync(c->blr_bsubs.p, bsubs.data(), (size_t)nsub * sizeof(BlrSub),
@@ -958,8 +989,8 @@ oras_status oras_compress_factors(oras_ctx c, double eps, int pmax, oras_blr_inf
   if (!items.empty())
     HIP_TRY(c, hipMemcpyAsync(c->blr_items.p, items.data(), items.size() * sizeof(BlrItem),
                               hipMemcpyHostToDevice, c->stream));
-  if (!addr.empty())
-    HIP_TRY(c, hipMemcpyAsync(c->blr_addr.p, addr.data(), addr.size() * sizeof(int),
+  if (!lists.empty())
+    HIP_TRY(c, hipMemcpyAsync(c->blr_lists.p, lists.data(), lists.size() * sizeof(int),
                               hipMemcpyHostToDevice, c->stream));
   if (c->factor_prec == ORAS_C64)
     launch_blr_compress<float>(sdev, c->blr_bsubs.as<BlrSub>(), tmp.blocks.as<BlrBlock>(), nblocks,
@@ -980,7 +1011,7 @@ oras_status oras_compress_factors(oras_ctx c, double eps, int pmax, oras_blr_inf
   pl.subs = sdev;
   pl.bsubs = c->blr_bsubs.as<BlrSub>();
   pl.items = c->blr_items.as<BlrItem>();
-  pl.addr = c->blr_addr.as<int>();
+  pl.lists = c->blr_lists.as<int>();
   pl.nsub = nsub;
   pl.max_sz = max_sz;
   pl.max_p = c->max_p;

@@ -183,10 +183,14 @@ void launch_cast(const double2* src, C<R>* dst, long long count, hipStream_t st)
 
 // ------------------------------------------------- block low-rank inverses --
 // Patch grid of one subdomain plane (rectangles of at most pmax x pmax nodes)
-// and the rows of its operand buffer (t rows 0..p-1, then projection rows).
+// and its rows of the operand buffer: the plane right-hand side in
+// patch-major order (each patch's rows padded to a multiple of 8, padding
+// rows zero), then the projection rows T.
 struct BlrSub {
   long long bt_off;      // first operand-buffer row of the subdomain
   int npx, npy;
+  int ptab;              // offset in the list array of the patches' first t rows
+  int pad_;
 };
 // One patch block (I, J) of one plane inverse: where compression writes it.
 struct BlrBlock {
@@ -198,24 +202,26 @@ struct BlrBlock {
   long long e_off;       // complex offset of the expansion operand of patch I
   long long p_off;       // complex offset of the projection operand of patch J (-1: none)
 };
-// One wave's work in a gather GEMM: rows of the output of one patch.
+// One wave's work in a segment GEMM: rows of the output of one patch.
+// Operand rows come in segments of consecutive operand-buffer rows whose
+// lengths are multiples of 8.
 struct BlrItem {
   int sub;               // -1: padding (no work)
   int patch;
   int rows;              // valid output rows
   int mpad;              // row stride of the operand storage ([k / 4][row][k % 4])
-  int K;                 // operand columns, a multiple of 4
+  int K;                 // operand columns, a multiple of 8
   int row0;              // first operand row of this item
-  int out_row;           // projection: operand-buffer row (from bt_off) of output row 0
-  int pad_;
+  int brow;              // projection: operand-buffer row (from bt_off) of the patch's t rows
+  int nseg;              // expansion: segments {k0, row, length, 0} at list_off
   long long a_off;       // complex offset of the operand storage
-  long long addr_off;    // expansion: offset of the K operand-buffer rows in the address list
+  long long list_off;    // projection: 32 destination rows; expansion: the segments
 };
 struct BlrApply {
   const SubDesc* subs;
   const BlrSub* bsubs;
   const BlrItem* items;
-  const int* addr;
+  const int* lists;
   int nsub, max_sz;
   long long max_p;
   // per plane k: [first, count) of the projection and expansion items
