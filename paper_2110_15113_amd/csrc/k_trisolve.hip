@@ -286,6 +286,23 @@ plane_gemm_f32_kernel(const SubDesc* __restrict__ subs, int nsub, int max_nt, in
   // accumulator item i of lane l: row 8 (i / 4) + 4 (l / 32) + i % 4, real column l % 32
   const bool final_plane = bwd || (k == sd.sz - 1);
   float* Yk = reinterpret_cast<float*>(ybuf + (sd.y_off + (long long)k * P) * s);
+  // backward: read every old value first (all loads in flight together)
+  float old[16][NB];
+#pragma unroll
+  for (int i = 0; i < 16; ++i)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) old[i][b] = 0.f;
+  if (bwd) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int row = I * TILE + 8 * (i / 4) + 4 * h + (i % 4);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int col = min(16 * (cbf + b) + (rr >> 1), s - 1);
+        old[i][b] = Yk[(long long)row * 2 * s + 2 * col + (rr & 1)];
+      }
+    }
+  }
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
     const int row = I * TILE + 8 * (i / 4) + 4 * h + (i % 4);
@@ -304,7 +321,7 @@ plane_gemm_f32_kernel(const SubDesc* __restrict__ subs, int nsub, int max_nt, in
       if (col >= s) continue;
       const int fi = 2 * col + (rr & 1);
       float val = acc[b][0][i] + acc[b][1][i];
-      if (bwd) val = yr[fi] - val;
+      if (bwd) val = old[i][b] - val;
       yr[fi] = val;
       if (zoff >= 0) reinterpret_cast<ZR*>(z + zoff)[fi] = (ZR)val;
     }
