@@ -49,6 +49,8 @@ def parse():
                     help="compress the plane inverses to block low-rank form with threshold EPS "
                          "(inside the timed step, after the factorisation)")
     ap.add_argument("--blr-pmax", type=int, default=8)
+    ap.add_argument("--no-blr-compare", action="store_true",
+                    help="skip the extra BLR (eps 1e-3) step reported beside the dense one")
     ap.add_argument("--freqs", type=int, default=0, metavar="K",
                     help="instead of the solve benchmark, solve config 4 at K frequencies in "
                          "flight on the GPU, and one after the other")
@@ -74,21 +76,22 @@ def copy_probe(mib: int):
                       "bytes_written_per_copy": 4 * n}), flush=True)
 
 
-def kernel_source_hash() -> str:
-    with open(os.path.join(ROOT, "paper_2110_15113_amd", "csrc", "k_trisolve.hip"), "rb") as f:
+def kernel_source_hash(src: str = "k_trisolve.hip") -> str:
+    with open(os.path.join(ROOT, "paper_2110_15113_amd", "csrc", src), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def traffic_for(workload: str, launches_bytes: float):
+def traffic_for(workload: str, summary: str = "plane_gemm_traffic.json",
+                src: str = "k_trisolve.hip"):
     """HBM traffic per launch from the committed rocprofv3 counter summary, if
     it was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "plane_gemm_traffic.json")
+    path = os.path.join(ROOT, "profiles", summary)
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
     entry = rec.get(workload)
-    if not entry or entry.get("kernel_sha") != kernel_source_hash():
+    if not entry or entry.get("kernel_sha") != kernel_source_hash(src):
         return None
     return entry.get("bytes_per_launch")
 
@@ -385,10 +388,19 @@ def main():
         roof = {"kernel": kname,
                 "bound": "mfma", "achieved": round(ach, 2), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(ach / peak, 4),
-                "traffic": None if args.blr is not None else traffic_for(w.name, bytes_per),
+                "traffic": (traffic_for(w.name, "blr_gemm_traffic.json", "k_blr.hip")
+                            if args.blr is not None else traffic_for(w.name)),
                 "algorithmic_bytes_per_launch": bytes_per, "algorithmic_flops_per_launch": flops_per,
                 "avg_launch_us": avg * 1e6, "launches": gl,
                 "achieved_GBps": round(bytes_per / avg / 1e9, 1)}
+        if args.blr is not None:
+            # the compressed blocks carry 8 s flops per stored entry but every
+            # plane step also moves the gathered and written rows: 14-15 flop/B,
+            # below the FP32 ridge (19.7), so the pair is bounded by HBM
+            gbps = bytes_per / avg / 1e9
+            roof.update({"bound": "hbm", "achieved": round(gbps, 1), "peak": PEAK["hbm_GBps"],
+                         "unit": "GB/s", "frac": round(gbps / PEAK["hbm_GBps"], 4),
+                         "achieved_TFLOPs": round(ach, 2)})
     rel_res = float(np.max(last.rel_res[:nrhs]))
     out = {
         "metric": "RHS solved/s to 1e-6 residual, mixed vs FP64 ORAS-FGMRES; 27-pt apply GB/s",
@@ -430,6 +442,30 @@ def main():
         out["blr"] = {k: blr_info[k] for k in ("eps", "pmax", "mean_rank", "max_rank", "lowrank",
                                                 "blocks", "t_compress")}
         out["blr"]["stored_fraction"] = blr_info["stored_entries"] / blr_info["dense_entries"]
+    elif P == oras.C64 and not args.no_blr_compare:
+        # the same step with BLR plane inverses (eps 1e-3, the paper's threshold):
+        # one untimed and one timed step on the same context
+        def step_blr():
+            S.assemble(vel, w.h, w.npml, w.omega, Q, prec=P)
+            S.factor(w.parts, overlap, P, interface=args.interface)
+            info = S.compress(1e-3, args.blr_pmax)
+            return S.solve(b, w.tol, restart=w.restart, maxit=w.maxit, out=xb), info
+        xb = torch.empty_like(b)
+        S.profile(False)
+        step_blr()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        rb, info = step_blr()
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - a
+        out["blr_same_workload"] = {
+            "eps": 1e-3, "pmax": args.blr_pmax, "ms_per_step": tb * 1e3,
+            "RHS_per_s": nrhs / tb, "t_compress_s": info["t_compress"],
+            "t_solve_s": rb.t_solve, "t_oras_s": rb.t_oras, "iterations": int(rb.total_iters),
+            "converged": bool(rb.converged.all()),
+            "max_rel_residual": float(np.max(rb.rel_res[:nrhs])),
+            "stored_fraction": info["stored_entries"] / info["dense_entries"],
+            "mean_rank": info["mean_rank"], "speedup_vs_dense_step": (elapsed / args.steps) / tb}
     if P == oras.C64 and not args.no_compare:
         # the same workload, same step, all complex128, in a fresh context
         x_mixed = x.clone()
