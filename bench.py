@@ -182,7 +182,7 @@ def bench_fwi(args):
     S.assemble(torch.as_tensor(w.vel_start, device=dev), w.h, w.npml, w.omega, None, prec=P)
     stats = {}
     fs = ForwardSetup(S, w.sources, w.receivers, w.parts, w.overlap, P, w.tol, w.restart,
-                      w.maxit, stats=stats, weights="follow")
+                      w.maxit, stats=stats, weights="follow", blr_eps=args.blr)
     mask = torch.zeros((w.nz, w.ny, w.nx), dtype=torch.float64, device=dev)
     p = w.npml
     mask[p:w.nz - p, p:w.ny - p, p:w.nx - p] = 1.0
@@ -209,10 +209,18 @@ def bench_fwi(args):
                 "bound": "mfma", "achieved": round(ach, 2), "peak": PEAK["fp64_mfma_TFLOPs"],
                 "unit": "TFLOP/s", "frac": round(ach / PEAK["fp64_mfma_TFLOPs"], 4),
                 "traffic": None, "avg_launch_us": gs / gl * 1e6, "launches": gl}
+        if args.blr is not None:
+            gbps = gb / gs / 1e9
+            roof.update({"kernel": "blr_gemm_f64_kernel projection + expansion (MFMA 16x16x4 "
+                                   "f64, BLR local substitutions)",
+                         "bound": "hbm", "achieved": round(gbps, 1), "peak": PEAK["hbm_GBps"],
+                         "unit": "GB/s", "frac": round(gbps / PEAK["hbm_GBps"], 4),
+                         "achieved_TFLOPs": round(ach, 2)})
     fw = [int(sum(i)) for i in stats.get("forward_iters", [])]
     ad = [int(sum(i)) for i in stats.get("adjoint_iters", [])]
     out = {
         "metric": "FWI model updates/s (L-BFGS, exact gradient, 32 sources)",
+        "blr_eps": args.blr,
         "value": len(res.history) / elapsed,
         "unit": "updates/s",
         "n_gpus": 1,
@@ -227,7 +235,8 @@ def bench_fwi(args):
         "config": {"workload": f"{w.name}: {w.nx}x{w.ny}x{w.nz} grid, h={w.h} m, {w.freq} Hz, "
                                f"{len(w.sources)} sources, {len(w.receivers)} receivers, ORAS "
                                f"{w.parts[0]}x{w.parts[1]}x{w.parts[2]} overlap {w.overlap}, "
-                               f"all complex128, tol {w.tol}"},
+                               f"all complex128, tol {w.tol}"
+                               f"{f', BLR eps {args.blr}' if args.blr is not None else ''}"},
         "objective_evaluations": evals,
         "ms_per_evaluation": elapsed / evals * 1e3,
         "misfit": [h["J"] for h in res.history] + [res.history[-1].get("J_new")],

@@ -44,6 +44,7 @@ class ForwardSetup:
     save_budget_bytes: float = 32e9
     stats: Optional[dict] = None
     weights: str = "frozen"       # or "follow": weights picked from G(m)
+    blr_eps: Optional[float] = None   # block low-rank plane inverses after each factorisation
 
 
 def _prepare(fs: ForwardSetup, m: torch.Tensor):
@@ -55,6 +56,8 @@ def _prepare(fs: ForwardSetup, m: torch.Tensor):
     if getattr(S, "_m_key", None) != key:
         S.set_m(m.detach().contiguous(), weights=fs.weights)
         S.factor(fs.parts, fs.overlap, fs.prec)
+        if fs.blr_eps is not None:
+            S.compress(fs.blr_eps)
         S._m_key = key
         S._m_ref = m
 
