@@ -559,35 +559,64 @@ blr_gemm_f64_kernel(const SubDesc* __restrict__ subs, const BlrSub* __restrict__
   const int bn = m >> 1;
   const bool im = (m & 1) != 0;
   const int c0 = 16 * cg;
+  // columns at or beyond s16 read column s16 - 1 (in bounds; their results are dropped)
+  int colc[2];
+#pragma unroll
+  for (int ns = 0; ns < 2; ++ns) colc[ns] = min(c0 + 8 * ns + bn, s16 - 1);
   f64x4 acc[RG][2];
 #pragma unroll
   for (int rg = 0; rg < RG; ++rg)
 #pragma unroll
     for (int ns = 0; ns < 2; ++ns) acc[rg][ns] = f64x4{0, 0, 0, 0};
-  auto group = [&](int kq, int rbase) {
+  // one 4-row group: lane kk takes operand row 4 kq + kk
+  auto load = [&](int kq, int rbase, double2 (&bv)[2], double2 (&a)[RG]) {
     const long long row = rbase + kk;
 #pragma unroll
+    for (int ns = 0; ns < 2; ++ns) bv[ns] = btc[row * s16 + colc[ns]];
+#pragma unroll
+    for (int rg = 0; rg < RG; ++rg)
+      a[rg] = A[((long long)kq * item.mpad + item.row0 + 16 * rg + m) * 4 + kk];
+  };
+  auto mma = [&](const double2 (&bv)[2], const double2 (&a)[RG]) {
+#pragma unroll
     for (int ns = 0; ns < 2; ++ns) {
-      const int col = c0 + 8 * ns + bn;
-      const double2 bv = col < s16 ? btc[row * s16 + col] : make_double2(0.0, 0.0);
-      const double b1 = im ? bv.y : bv.x;
-      const double b2 = im ? bv.x : -bv.y;
+      const double b1 = im ? bv[ns].y : bv[ns].x;
+      const double b2 = im ? bv[ns].x : -bv[ns].y;
 #pragma unroll
       for (int rg = 0; rg < RG; ++rg) {
-        const double2 a = A[((long long)kq * item.mpad + item.row0 + 16 * rg + m) * 4 + kk];
-        acc[rg][ns] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b1, acc[rg][ns], 0, 0, 0);
-        acc[rg][ns] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b2, acc[rg][ns], 0, 0, 0);
+        acc[rg][ns] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rg].x, b1, acc[rg][ns], 0, 0, 0);
+        acc[rg][ns] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rg].y, b2, acc[rg][ns], 0, 0, 0);
       }
     }
   };
+  // two groups in flight in two register sets, as in the FP32 kernel (runs
+  // are multiples of 8 rows: an even number of groups; nothing conditional)
+  auto run = [&](int q0, int q1, int rbase0) {
+    double2 b0[2], b1[2], a0[RG], a1[RG];
+    auto ld = [&](int kq, double2 (&bv)[2], double2 (&a)[RG]) {
+      const int g = min(kq, q1 - 1);
+      load(g, rbase0 + 4 * (g - q0), bv, a);
+    };
+    ld(q0, b0, a0);
+    ld(q0 + 1, b1, a1);
+    __builtin_amdgcn_sched_barrier(0);
+    for (int kq = q0; kq < q1; kq += 2) {
+      mma(b0, a0);
+      __builtin_amdgcn_sched_barrier(0);
+      ld(kq + 2, b0, a0);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(b1, a1);
+      __builtin_amdgcn_sched_barrier(0);
+      ld(kq + 3, b1, a1);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  };
   if (MODE == 0) {
-    const int nkq = item.K >> 2;
-    for (int kq = 0; kq < nkq; ++kq) group(kq, item.brow + 4 * kq);
+    run(0, item.K >> 2, item.brow);
   } else {
     for (int sg = 0; sg < item.nseg; ++sg) {
       const int4 seg = *reinterpret_cast<const int4*>(lists + item.list_off + 4 * sg);
-      const int q0 = seg.x >> 2, q1 = (seg.x + seg.z) >> 2;
-      for (int kq = q0; kq < q1; ++kq) group(kq, seg.y + 4 * (kq - q0));
+      run(seg.x >> 2, (seg.x + seg.z) >> 2, seg.y);
     }
   }
   if (MODE == 0) {
