@@ -9,7 +9,11 @@ properties that hold at any size:
   * the local solve of one interior subdomain: the ORAS apply at that
     subdomain's owned nodes equals the oracle's direct solve with its B_j;
   * mixed precision: the solution at tol 1e-6 is within 1e-4 (relative L2) of
-    the FP64 GPU solution at tol 1e-10 (whose residual is certified above).
+    the FP64 GPU solution at tol 1e-10 (whose residual is certified above);
+  * BLR plane inverses (config 5, eps 1e-3, the benchmark's BLR step): the
+    compressed local solve of one interior subdomain against the oracle's
+    BLR plane recursion, the certified residual, and the solution within 1e-4
+    of the FP64 solution.
 """
 import gc
 
@@ -17,7 +21,7 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import direct, operator as op, oras as ooras
+from oracle import blr as oblr, direct, operator as op, oras as ooras
 from paper_2110_15113_amd import workloads as wl
 
 from gpu_util import need_gpu, say
@@ -76,7 +80,12 @@ def _check_residual(S, F, w, b, x, tol):
         assert np.abs(rw - rg).max() <= 1e-11 * scale, lo
 
 
-def _check_local_solve(S, F, w, tol_rel):
+def _check_local_solve(S, F, w, tol_rel, blr_eps=None):
+    """The ORAS apply at one interior subdomain's owned nodes against the
+    oracle's local solve with its B_j (exact; with blr_eps, also the oracle's
+    BLR plane recursion: the GPU result must be much closer to it than the
+    compression error, and no further from the exact solve than the
+    oracle's own compression error allows)."""
     subs = ooras.partition((w.nx, w.ny, w.nz), w.parts, w.overlap)
     inner = [s for s in subs if all(s.lo[a] > 0 and s.hi[a] < (w.nx, w.ny, w.nz)[a]
                                     for a in range(3))] or subs
@@ -86,13 +95,29 @@ def _check_local_solve(S, F, w, tol_rel):
     z = S.apply_M(torch.as_tensor(v, device=S.device)).cpu().numpy()
     bs = tuple(s.hi[a] - s.lo[a] for a in range(3))
     B = op.csr_from_coeffs(op.row_coeffs(F, s.lo, s.hi, restrict=True))
-    lu = direct.BlockTridiagLU(B, bs[0] * bs[1], bs[2])
     box = (slice(None),) + tuple(slice(s.lo[a], s.hi[a]) for a in (2, 1, 0))
-    y = lu.solve(v[box].reshape(2, -1).T).T.reshape((2, bs[2], bs[1], bs[0]))
     own = (slice(None),) + tuple(slice(s.olo[a] - s.lo[a], s.ohi[a] - s.lo[a]) for a in (2, 1, 0))
     dst = (slice(None),) + tuple(slice(s.olo[a], s.ohi[a]) for a in (2, 1, 0))
-    err = np.linalg.norm(z[dst] - y[own]) / np.linalg.norm(y[own])
-    assert err <= tol_rel, err
+
+    def local(solver):
+        y = solver.solve(v[box].reshape(2, -1).T).T.reshape((2, bs[2], bs[1], bs[0]))
+        return y[own]
+
+    def rel_(a, b):
+        return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+    ye = local(direct.BlockTridiagLU(B, bs[0] * bs[1], bs[2]))
+    if blr_eps is None:
+        err = rel_(z[dst], ye)
+        assert err <= tol_rel, err
+        return
+    yb = local(oblr.PlaneSolver(B, bs[0], bs[1], bs[2], blr_eps))
+    comp = rel_(yb, ye)                       # the oracle's compression error
+    err_b, err_e = rel_(z[dst], yb), rel_(z[dst], ye)
+    say(f"BLR local solve: oracle compression {comp:.2e}, GPU vs oracle BLR {err_b:.2e}, "
+        f"GPU vs exact {err_e:.2e}")
+    assert err_b <= max(tol_rel, 0.25 * comp), (err_b, comp)
+    assert err_e <= 2.0 * comp + tol_rel, (err_e, comp)
 
 
 @pytest.mark.parametrize("cfg", [2, 4])
@@ -128,6 +153,16 @@ def test_mixed_workload_against_fp64(cfg):
     assert rm.converged.all() and rm.rel_res.max() <= w.tol
     _check_residual(S, F, w, b, rm.x, w.tol)
     xm = rm.x.clone()
+    xb = None
+    if cfg == 5:
+        say("full-size mixed config 5 with BLR plane inverses")
+        S.compress(1e-3)
+        _check_local_solve(S, F, w, 1e-3, blr_eps=1e-3)
+        rb = S.solve(b, w.tol, restart=w.restart, maxit=w.maxit)
+        assert rb.converged.all() and rb.rel_res.max() <= w.tol
+        _check_residual(S, F, w, b, rb.x, w.tol)
+        xb = rb.x.clone()
+        del rb
     S.close()
     del S, rm
     gc.collect()
@@ -142,6 +177,11 @@ def test_mixed_workload_against_fp64(cfg):
            / torch.linalg.vector_norm(rt.x.reshape(-1))).item()
     say(f"config {cfg}: mixed(1e-6) vs fp64(1e-10) relative L2 = {err:.3e}")
     assert err <= 1e-4, err
+    if xb is not None:
+        errb = (torch.linalg.vector_norm((xb - rt.x).reshape(-1))
+                / torch.linalg.vector_norm(rt.x.reshape(-1))).item()
+        say(f"config {cfg}: mixed BLR(1e-6) vs fp64(1e-10) relative L2 = {errb:.3e}")
+        assert errb <= 1e-4, errb
     S.close()
     gc.collect()
     torch.cuda.empty_cache()
