@@ -108,3 +108,25 @@ def test_blr_solve_config1(prec):
         assert rel(x, u) < (1e-4 if prec == 1 else 1e-6), rel(x, u)
         its[blr] = int(r.iters.max())
     assert its[True] <= its[False] + 5, its
+
+
+def test_blr_with_pml_interfaces_matches_oracle():
+    """BLR compression of the plane inverses of PML-interface subdomain
+    matrices (sec. 2.2 note on the overlap; sec. 3 BLR), FP64 ranks and
+    apply against the oracle."""
+    need_gpu()
+    c = dict(n=(19, 17, 15), parts=(2, 2, 1), ov=3, npml=2, q=50.0, pmax=6, nrhs=5)
+    w = wl.small_random(c["n"], npml=c["npml"], q=c["q"], seed=13, parts=c["parts"],
+                        overlap=c["ov"])
+    say("blr with pml interfaces")
+    F = oracle_fields(w)
+    M = oblr.OrasBLR(F, c["parts"], c["ov"], 1e-3, c["pmax"], interface="pml")
+    S = setup(w, prec=2, parts=c["parts"], overlap=c["ov"], interface="pml")
+    S.compress(1e-3, c["pmax"])
+    for j, sol in enumerate(M.solvers):
+        for k, plane in enumerate(sol.inv):
+            assert np.array_equal(S.blr_ranks(j, k), plane.rank), (j, k)
+    x = rand_field((w.nz, w.ny, w.nx), c["nrhs"], 8)
+    got = S.apply_M(to_dev(x, S)).cpu().numpy()
+    ref = M.apply(x)
+    assert rel(got, ref) < 1e-9, rel(got, ref)
