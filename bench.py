@@ -445,7 +445,16 @@ def main():
         "t_oras_s": last.t_oras,
         "t_ortho_s": last.t_ortho,
         "stencil_GBps": sten_GBps,
+        "stencil_hbm_frac": (sten_GBps / PEAK["hbm_GBps"]) if sten_GBps else None,
+        "dof_RHS_per_s": w.n * nrhs * args.steps / elapsed,
         "roofline": roof,
+        # the paper's own figure for its pseudo-block ORAS solve, with the
+        # hardware it names (another problem, machine and tolerance: context only)
+        "paper_context": {"value": 0.506, "unit": "RHS/s", "dof_RHS_per_s": 67.5e6 * 0.506,
+                          "workload": "GO_3D_OBS 3.75 Hz, 67.5 M dof, 130 RHS, single "
+                                      "precision, MUMPS-BLR local factors, CGS",
+                          "hardware": "1344 Intel Haswell E5-2690v3 cores (56 nodes)",
+                          "source": "Table 4"},
     }
     if blr_info:
         out["blr"] = {k: blr_info[k] for k in ("eps", "pmax", "mean_rank", "max_rank", "lowrank",
