@@ -148,3 +148,64 @@ def gpu_objective(fs, d_obs: torch.Tensor) -> Objective:
         return J.item(), x.grad.detach()
 
     return f
+
+
+class MultiFrequencyObjective:
+    """J(m) = sum over frequencies of 1/2 sum |P A_f(m)^{-1} b_s - d_obs_f|^2 and
+    its gradient, with every frequency in flight on the GPU at once (sec. 1:
+    frequency-domain FWI inverts a few frequencies; each has its own operator
+    and factors).  One context and HIP stream per frequency
+    (``frequencies.FrequencyBatch``, assembled on the start model, which fixes
+    the PML and Q); each evaluation runs, per frequency and in its own host
+    thread, set_m, factorisation (optionally BLR), the forward block solve,
+    sampling, the adjoint (conjugate) solve of the spread residuals and the
+    gradient -- the steps of ``autograd.HelmholtzData`` called directly."""
+
+    def __init__(self, fb, sources, receivers, d_obs, parts, overlap: int = 2,
+                 tol: float = 1e-8, restart: int = 30, maxit: int = 2000,
+                 weights: str = "follow", blr_eps: Optional[float] = None,
+                 concurrent: bool = True):
+        if len(d_obs) != len(fb.items):
+            raise ValueError("one observed-data block per frequency")
+        self.fb, self.sources, self.receivers = fb, sources, receivers
+        self.d_obs = d_obs
+        self.parts, self.overlap, self.tol = parts, overlap, tol
+        self.restart, self.maxit = restart, maxit
+        self.weights, self.blr_eps, self.concurrent = weights, blr_eps, concurrent
+        self.stats = {"iters": []}
+
+    def __call__(self, m: torch.Tensor):
+        n = len(self.fb.items)
+        Js = [0.0] * n
+        gs = [None] * n
+        iters = [None] * n
+        m = m.detach().contiguous()
+
+        def one(i, it):
+            S = it.solver
+            S.set_m(m, weights=self.weights)
+            S.factor(self.parts, self.overlap, self.fb.prec)
+            if self.blr_eps is not None:
+                S.compress(self.blr_eps)
+            b = S.point_sources(self.sources)
+            r = S.solve(b, self.tol, restart=self.restart, maxit=self.maxit)
+            if not r.converged.all():
+                raise RuntimeError("forward solve did not converge")
+            res = S.sample(r.x, self.receivers) - self.d_obs[i]
+            Js[i] = 0.5 * float(res.abs().pow(2).sum())
+            ra = S.solve(S.spread(res.contiguous(), self.receivers), self.tol,
+                         restart=self.restart, maxit=self.maxit, conj=True)
+            if not ra.converged.all():
+                raise RuntimeError("adjoint solve did not converge")
+            gs[i] = S.gradient(r.x, ra.x, weights=self.weights == "follow")
+            iters[i] = (int(r.total_iters), int(ra.total_iters))
+
+        self.fb._run(one, self.concurrent)
+        self.stats["iters"].append(iters)
+        g = gs[0].clone()
+        for x in gs[1:]:
+            g += x
+        # the per-frequency tensors were made on the frequencies' streams: finish
+        # the sum before they return to the allocator
+        torch.cuda.synchronize(g.device)
+        return sum(Js), g
