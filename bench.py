@@ -49,6 +49,10 @@ def parse():
                     help="compress the plane inverses to block low-rank form with threshold EPS "
                          "(inside the timed step, after the factorisation)")
     ap.add_argument("--blr-pmax", type=int, default=8)
+    ap.add_argument("--krylov-in-prec", choices=["auto", "c64", "c128"], default="auto",
+                    help="precision of A z_j in the Arnoldi step (auto: the stencil's)")
+    ap.add_argument("--z-prec", choices=["auto", "c64", "c128"], default="auto",
+                    help="storage of the preconditioned basis Z (auto: the factors')")
     ap.add_argument("--no-blr-compare", action="store_true",
                     help="skip the extra BLR (eps 1e-3) step reported beside the dense one")
     ap.add_argument("--freqs", type=int, default=0, metavar="K",
@@ -424,13 +428,16 @@ def main():
     x = torch.empty_like(b)
 
     blr_info = {}
+    pcode = {"auto": 0, "c64": oras.C64, "c128": oras.C128}
+    kp, zp = pcode[args.krylov_in_prec], pcode[args.z_prec]
 
     def step():
         S.assemble(vel, w.h, w.npml, w.omega, Q, prec=P)
         S.factor(w.parts, overlap, P, interface=args.interface)
         if args.blr is not None:
             blr_info.update(S.compress(args.blr, args.blr_pmax))
-        return S.solve(b, w.tol, restart=w.restart, maxit=w.maxit, out=x)
+        return S.solve(b, w.tol, restart=w.restart, maxit=w.maxit, out=x, krylov_in_prec=kp,
+                       z_prec=zp)
 
     for _ in range(args.warmup):
         step()
@@ -505,7 +512,9 @@ def main():
                                f"{w.parts[2]} overlap {overlap}"
                                f"{', PML interfaces' if args.interface == 'pml' else ''}"
                                f"{f', BLR eps {args.blr} patches <= {args.blr_pmax}^2' if args.blr is not None else ''}, "
-                               f"{'complex64 stencil+factors, FP64 FGMRES' if P == oras.C64 else 'all complex128'},"
+                               f"{'complex64 stencil+factors, FP64 FGMRES' if P == oras.C64 else 'all complex128'}"
+                               f"{f', A z_j in {args.krylov_in_prec}' if kp else ''}"
+                               f"{f', Z in {args.z_prec}' if zp else ''},"
                                f" restart {w.restart}, tol {w.tol}",
                    "nrhs": nrhs, "n": w.n, "tol": w.tol, "restart": w.restart,
                    "precision": prec},

@@ -93,7 +93,12 @@ typedef struct {
   int restart;         /* FGMRES restart length m (1..200) */
   int maxit;           /* maximum Arnoldi steps per column (>= 1) */
   int flags;           /* ORAS_CONJ | ORAS_X0 */
-  int reserved;
+  int krylov_in_prec;  /* precision of the product A z_j inside the Arnoldi
+                          step: 0 = the assembled stencil precision, ORAS_C64
+                          (needs a context assembled in ORAS_C64) or ORAS_C128 */
+  int z_prec;          /* storage of the preconditioned basis Z: 0 = the factor
+                          precision, ORAS_C128, or ORAS_C64 (needs ORAS_C64
+                          factors) */
 } oras_solve_opts;
 
 typedef struct {
@@ -178,10 +183,17 @@ oras_status oras_factor_subdomains_ex(oras_ctx ctx, const int parts[3], int over
 
 /* Solve A x_c = b_c for nrhs columns with pseudo-block right-preconditioned
  * FGMRES (sec. 2.1, sec. 2.2): FP64 Arnoldi basis, classical Gram-Schmidt,
- * complex Givens, FP64 true residual at each restart; the stencil and ORAS
- * run in the assembled / factored precisions.  b_dev, x_dev: (nrhs,nz,ny,nx)
- * complex128.  tol in (0, 1).  Columns with b = 0 return x = 0 (converged).
- * Returns ORAS_W_NOT_CONVERGED when a column reached maxit. */
+ * complex Givens, FP64 true residual at each restart.  ORAS runs in the
+ * factored precision; by default the product A z_j and the basis Z follow
+ * the assembled / factored precisions (all complex64 in mixed mode), and
+ * opts->krylov_in_prec / z_prec select complex128 for either (sec. 3: the
+ * paper's single-precision runs factor in single precision and keep the
+ * Krylov solver in double).  The context must be assembled and factored in
+ * the same precision.  b_dev, x_dev: (nrhs,nz,ny,nx) complex128.  tol in
+ * (0, 1).  opts NULL = {30, 1000, 0, 0, 0}.  Columns with b = 0 return x = 0
+ * (converged).  Returns ORAS_W_NOT_CONVERGED when a column reached maxit,
+ * ORAS_E_ARG for an out-of-range option or a precision the context cannot
+ * serve. */
 oras_status oras_solve(oras_ctx ctx, const void* b_dev, void* x_dev, int nrhs, double tol,
                        const oras_solve_opts* opts, oras_solve_info* info);
 

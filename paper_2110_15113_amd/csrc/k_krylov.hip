@@ -374,6 +374,14 @@ __global__ void cast_kernel(const double2* __restrict__ src, C<R>* __restrict__ 
   dst[i] = v;
 }
 
+__global__ void widen_kernel(const float2* __restrict__ src, double2* __restrict__ dst,
+                             long long count) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const float2 v = src[i];
+  dst[i] = make_double2((double)v.x, (double)v.y);
+}
+
 inline unsigned blocks_for(long long work, int bs) { return (unsigned)((work + bs - 1) / bs); }
 inline int group_threads(int s) {
   int G = 256 / s;
@@ -480,5 +488,9 @@ void launch_cast(const double2* src, C<R>* dst, long long count, hipStream_t st)
 }
 template void launch_cast<float>(const double2*, float2*, long long, hipStream_t);
 template void launch_cast<double>(const double2*, double2*, long long, hipStream_t);
+void launch_widen(const float2* src, double2* dst, long long count, hipStream_t st) {
+  hipLaunchKernelGGL(widen_kernel, dim3(blocks_for(count, 256)), dim3(256), 0, st, src, dst,
+                     count);
+}
 
 }  // namespace oras

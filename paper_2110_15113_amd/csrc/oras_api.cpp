@@ -1115,15 +1115,25 @@ oras_status oras_solve(oras_ctx c, const void* b_dev, void* x_dev, int nrhs, dou
   if (!b_dev || !x_dev) return fail(c, ORAS_E_ARG, "null b or x");
   if (nrhs < 1 || nrhs > 256) return fail(c, ORAS_E_ARG, "nrhs must be 1..256");
   if (!(tol > 0.0 && tol < 1.0)) return fail(c, ORAS_E_ARG, "tol must be in (0, 1)");
-  oras_solve_opts o = {30, 1000, 0, 0};
+  oras_solve_opts o = {30, 1000, 0, 0, 0};
   if (opts) o = *opts;
   if (o.restart < 1 || o.restart > 200) return fail(c, ORAS_E_ARG, "restart must be 1..200");
   if (o.maxit < 1) return fail(c, ORAS_E_ARG, "maxit must be >= 1");
   if (o.flags & ~(ORAS_CONJ | ORAS_X0)) return fail(c, ORAS_E_ARG, "unknown flags");
+  auto prec_ok = [](int p) { return p == 0 || p == ORAS_C64 || p == ORAS_C128; };
+  if (!prec_ok(o.krylov_in_prec)) return fail(c, ORAS_E_ARG, "krylov_in_prec must be 0, C64 or C128");
+  if (!prec_ok(o.z_prec)) return fail(c, ORAS_E_ARG, "z_prec must be 0, C64 or C128");
   if (!c->assembled) return fail(c, ORAS_E_STATE, "solve before assemble");
   if (!c->factored) return fail(c, ORAS_E_STATE, "solve before factor_subdomains");
   if (c->stencil_prec != c->factor_prec)
     return fail(c, ORAS_E_ARG, "stencil and factor precisions must match");
+  // precision of the product A z_j and of the stored basis Z
+  const int kprec = o.krylov_in_prec ? o.krylov_in_prec : c->stencil_prec;
+  const int zprec = o.z_prec ? o.z_prec : c->factor_prec;
+  if (kprec == ORAS_C64 && c->stencil_prec != ORAS_C64)
+    return fail(c, ORAS_E_ARG, "krylov_in_prec C64 needs a context assembled in C64");
+  if (zprec == ORAS_C64 && c->factor_prec != ORAS_C64)
+    return fail(c, ORAS_E_ARG, "z_prec C64 needs C64 factors");
   TRY(check_device(c));
   const double t0 = now();
   const hipStream_t st = c->stream;
@@ -1131,13 +1141,19 @@ oras_status oras_solve(oras_ctx c, const void* b_dev, void* x_dev, int nrhs, dou
   const long long s = pad_s(nrhs);
   const long long n = c->n;
   const long long ns = n * s;
-  const bool mixed = (c->factor_prec == ORAS_C64);
-  const size_t zsz = mixed ? sizeof(float2) : sizeof(double2);
+  const bool z64 = (zprec == ORAS_C64);
+  const size_t zsz = z64 ? sizeof(float2) : sizeof(double2);
+  // A z_j in another precision than Z is stored in goes through a converted copy
+  const bool convert = (kprec == ORAS_C64) != z64;
   const int nblk = nblk_for(n);
   {
     double need = 0;
     if (!c->V.p || c->ws_s < s || c->ws_m < m) need += (double)ns * ((m + 1) * 16.0 + m * zsz + 2 * 16.0);
     TRY(check_free(c, need));
+  }
+  if (convert) {
+    if (kprec == ORAS_C64) TRY(dev_alloc(c, c->Tmp64, (size_t)ns * sizeof(float2)));
+    else TRY(dev_alloc(c, c->Tmp, (size_t)ns * sizeof(double2)));
   }
   if (c->ws_s < s || c->ws_m < m) c->release_workspace();
   TRY(dev_alloc(c, c->V, (size_t)((m + 1) * ns) * sizeof(double2)));
@@ -1221,14 +1237,25 @@ oras_status oras_solve(oras_ctx c, const void* b_dev, void* x_dev, int nrhs, dou
       double2* Vj = V + (size_t)j * ns;
       double2* Vn = V + (size_t)(j + 1) * ns;
       HIP_TRY(c, hipEventRecord(ev[0], st));
-      TRY(oras_apply_internal(c, Vj, scale + j * s, Zj, (int)s, !mixed, nrhs));
+      TRY(oras_apply_internal(c, Vj, scale + j * s, Zj, (int)s, !z64, nrhs));
       HIP_TRY(c, hipEventRecord(ev[1], st));
-      if (mixed)
-        launch_stencil<float>(c->coef64.as<float2>(), (const float2*)Zj, nullptr, Vn, c->nx, c->ny,
-                              c->nz, (int)s, st);
-      else
-        launch_stencil<double>(c->coef128.as<double2>(), (const double2*)Zj, nullptr, Vn, c->nx,
-                               c->ny, c->nz, (int)s, st);
+      if (kprec == ORAS_C64) {
+        const float2* zin = (const float2*)Zj;
+        if (convert) {
+          launch_cast<float>((const double2*)Zj, c->Tmp64.as<float2>(), ns, st);
+          zin = c->Tmp64.as<float2>();
+        }
+        launch_stencil<float>(c->coef64.as<float2>(), zin, nullptr, Vn, c->nx, c->ny, c->nz,
+                              (int)s, st);
+      } else {
+        const double2* zin = (const double2*)Zj;
+        if (convert) {
+          launch_widen((const float2*)Zj, c->Tmp.as<double2>(), ns, st);
+          zin = c->Tmp.as<double2>();
+        }
+        launch_stencil<double>(c->coef128.as<double2>(), zin, nullptr, Vn, c->nx, c->ny, c->nz,
+                               (int)s, st);
+      }
       HIP_TRY(c, hipEventRecord(ev[2], st));
       launch_cgs_dot(V, ns, j + 1, Vn, n, (int)s, dpart, nblk, st);
       launch_cgs_finish_dot(dpart, nblk, j + 1, (int)s, scale, hv, hs, st);
@@ -1257,7 +1284,7 @@ oras_status oras_solve(oras_ctx c, const void* b_dev, void* x_dev, int nrhs, dou
     }
     if (result != ORAS_OK) break;
     launch_backsolve(m, (int)s, H, g, jc, y, st);
-    if (mixed)
+    if (z64)
       launch_update_x<float2>(c->Z.as<float2>(), ns, y, jc, X, n, (int)s, st);
     else
       launch_update_x<double2>(c->Z.as<double2>(), ns, y, jc, X, n, (int)s, st);

@@ -180,6 +180,8 @@ void launch_gradient(const OpView& op, const double2* qfac, const double2* u, co
                      int nrhs, double* g, hipStream_t st);
 template <typename R>
 void launch_cast(const double2* src, C<R>* dst, long long count, hipStream_t st);
+// dst = src exactly (complex64 -> complex128)
+void launch_widen(const float2* src, double2* dst, long long count, hipStream_t st);
 
 // ------------------------------------------------- block low-rank inverses --
 // Patch grid of one subdomain plane (rectangles of at most pmax x pmax nodes)

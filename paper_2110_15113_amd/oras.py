@@ -54,7 +54,7 @@ GRAD_WEIGHTS = 1       # gradient flag
 
 class SolveOpts(ct.Structure):
     _fields_ = [("restart", ct.c_int), ("maxit", ct.c_int), ("flags", ct.c_int),
-                ("reserved", ct.c_int)]
+                ("krylov_in_prec", ct.c_int), ("z_prec", ct.c_int)]
 
 
 class SolveInfo(ct.Structure):
@@ -267,7 +267,10 @@ class Solver:
     # -- solve -------------------------------------------------------------
     def solve(self, b: torch.Tensor, tol: float, restart: int = 30, maxit: int = 1000,
               conj: bool = False, x0: Optional[torch.Tensor] = None,
-              out: Optional[torch.Tensor] = None) -> SolveResult:
+              out: Optional[torch.Tensor] = None, krylov_in_prec: int = 0,
+              z_prec: int = 0) -> SolveResult:
+        """krylov_in_prec / z_prec: precision of A z_j in the Arnoldi step and
+        of the stored basis Z (0: the context's stencil / factor precision)."""
         nrhs = b.shape[0]
         _need(b, torch.complex128, self.device, (nrhs,) + self.shape, name="b")
         flags = CONJ if conj else 0
@@ -282,7 +285,7 @@ class Solver:
         rr = (ct.c_double * nrhs)()
         cv = (ct.c_int * nrhs)()
         info = SolveInfo(it, rr, cv, 0.0, 0.0, 0.0, 0.0, 0, 0)
-        opts = SolveOpts(int(restart), int(maxit), flags, 0)
+        opts = SolveOpts(int(restart), int(maxit), flags, int(krylov_in_prec), int(z_prec))
         rc = self._check(lib().oras_solve(self._ctx, _ptr(b), _ptr(out), nrhs, float(tol),
                                           ct.byref(opts), ct.byref(info)), allow_warn=True)
         return SolveResult(out, np.array(it[:]), np.array(rr[:]), np.array(cv[:], dtype=bool),

@@ -85,6 +85,13 @@ def test_host_only_context_validates_before_device():
         assert L.oras_solve(ctx, fake, fake, 1, 1e-6, ct.byref(bado), None) == 1
         flg = oras.SolveOpts(30, 100, 64, 0)
         assert L.oras_solve(ctx, fake, fake, 1, 1e-6, ct.byref(flg), None) == 1
+        # precisions of A z_j and of Z: values first, then the missing state
+        for kp, zp in ((3, 0), (0, 3), (-1, 0), (0, 5)):
+            o = oras.SolveOpts(30, 100, 0, kp, zp)
+            assert L.oras_solve(ctx, fake, fake, 1, 1e-6, ct.byref(o), None) == 1
+        for kp, zp in ((1, 0), (2, 2), (1, 2), (2, 1)):
+            o = oras.SolveOpts(30, 100, 0, kp, zp)
+            assert L.oras_solve(ctx, fake, fake, 1, 1e-6, ct.byref(o), None) == 2
         assert L.oras_apply_M(ctx, fake, fake, 1) == 2
         assert L.oras_apply_A(ctx, fake, fake, 1, 2) == 2
         assert L.oras_set_m(ctx, fake) == 2

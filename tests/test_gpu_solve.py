@@ -116,3 +116,50 @@ def test_not_converged_warning_and_maxit():
     S = setup(w, prec=2, parts=w.parts)
     r = S.solve(to_dev(b, S), 1e-12, restart=2, maxit=3)
     assert r.status == 100 and not r.converged.any() and r.total_iters == 3
+
+
+def test_krylov_and_basis_precisions():
+    """opts.krylov_in_prec / z_prec on complex64 factors: every combination
+    meets the FP64 residual bar; a basis stored in complex128 holds the
+    complex64 local solutions exactly, so the pairs that differ only in the
+    storage of Z give bitwise equal results; the paper's single-precision
+    setting (factors in single, Krylov in double: A z_j in complex128)
+    reaches an FP64 tolerance."""
+    need_gpu()
+    from paper_2110_15113_amd import oras
+    w = wl.small_random((24, 22, 20), npml=4, q=90.0, nsrc=4, seed=21, parts=(2, 2, 2))
+    say("krylov / basis precisions on c64 factors")
+    b = op.point_sources(oracle_fields(w), w.sources)
+    u, A = _direct(w, b)
+    S = setup(w, prec=1, parts=w.parts)
+    bd = to_dev(b, S)
+    tol = 1e-6
+    out = {}
+    for kp, zp in ((0, 0), (1, 1), (1, 2), (2, 2), (2, 1)):
+        r = S.solve(bd, tol, restart=20, krylov_in_prec=kp, z_prec=zp)
+        assert r.converged.all(), (kp, zp)
+        x = r.x.cpu().numpy()
+        for c in range(b.shape[0]):
+            res = np.linalg.norm(A @ x[c].ravel() - b[c].ravel()) / np.linalg.norm(b[c])
+            assert res <= tol * 1.0001, (kp, zp, c, res)
+        assert rel(x, u) < 1e-4, (kp, zp, rel(x, u))
+        out[kp, zp] = (x, r.iters.copy())
+    for a, c in (((0, 0), (1, 1)), ((1, 1), (1, 2)), ((2, 2), (2, 1))):
+        assert np.array_equal(out[a][0], out[c][0]), (a, c)
+        assert np.array_equal(out[a][1], out[c][1]), (a, c)
+    r = S.solve(bd, 1e-10, restart=20, maxit=400, krylov_in_prec=2, z_prec=2)
+    assert r.converged.all()
+    x = r.x.cpu().numpy()
+    for c in range(b.shape[0]):
+        res = np.linalg.norm(A @ x[c].ravel() - b[c].ravel()) / np.linalg.norm(b[c])
+        assert res <= 1e-10 * 1.0001, (c, res)
+    assert rel(x, u) < 1e-7, rel(x, u)
+    # complex64 work needs a complex64 context
+    S2 = setup(w, prec=2, parts=w.parts)
+    bd2 = to_dev(b, S2)
+    for kp, zp in ((1, 0), (0, 1)):
+        with pytest.raises(oras.OrasError):
+            S2.solve(bd2, tol, krylov_in_prec=kp, z_prec=zp)
+    r0 = S2.solve(bd2, tol, restart=20)
+    r1 = S2.solve(bd2, tol, restart=20, krylov_in_prec=2, z_prec=2)
+    assert torch.equal(r0.x, r1.x)
