@@ -81,6 +81,7 @@ def test_host_only_context_validates_before_device():
         assert L.oras_solve(ctx, fake, fake, 1, 1e-6, ct.byref(opts), None) == 2
         assert L.oras_solve(ctx, fake, fake, 1, 0.0, ct.byref(opts), None) == 1
         assert L.oras_solve(ctx, fake, fake, 0, 1e-6, ct.byref(opts), None) == 1
+        assert L.oras_solve(ctx, fake, fake, 257, 1e-6, ct.byref(opts), None) == 1
         bado = oras.SolveOpts(0, 100, 0, 0)
         assert L.oras_solve(ctx, fake, fake, 1, 1e-6, ct.byref(bado), None) == 1
         flg = oras.SolveOpts(30, 100, 64, 0)

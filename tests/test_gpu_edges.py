@@ -1,0 +1,97 @@
+"""Edge cases of the GPU path at the limits the library accepts: the widest
+right-hand-side block (256 columns), the longest restart (200), the largest
+subdomain plane (8192 nodes), the thinnest boxes (2 nodes) and zero overlap."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import blr as oblr, direct, operator as op, oras as ooras
+from paper_2110_15113_amd import workloads as wl
+
+from gpu_util import need_gpu, oracle_fields, rand_field, rel, say, setup, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def test_widest_block_of_right_hand_sides():
+    """256 columns (the maximum): ORAS apply in both precisions and with BLR
+    plane inverses against the oracle, and an FP64 block solve against the
+    direct solution."""
+    need_gpu()
+    w = wl.small_random((14, 13, 12), npml=2, q=70.0, seed=31, parts=(2, 2, 1), overlap=2)
+    say("256 right-hand sides")
+    F = oracle_fields(w)
+    x = rand_field((w.nz, w.ny, w.nx), 256, 17)
+    ref = ooras.ORAS(F, w.parts, w.overlap).apply(x)
+    S = setup(w, prec=2, parts=w.parts)
+    assert rel(S.apply_M(to_dev(x, S)).cpu().numpy(), ref) < 1e-9
+    S32 = setup(w, prec=1, parts=w.parts)
+    assert rel(S32.apply_M(to_dev(x, S32)).cpu().numpy(), ref) < 1e-3
+    S32.compress(1e-3, 4)
+    ref_blr = oblr.OrasBLR(F, w.parts, w.overlap, 1e-3, 4).apply(x)
+    assert rel(S32.apply_M(to_dev(x, S32)).cpu().numpy(), ref_blr) < 1e-3
+    A = op.assemble(F)
+    b = x[:, ::-1].copy()                   # any 256 right-hand sides
+    u = direct.solve(A, F.shape, b)
+    r = S.solve(to_dev(b, S), 1e-10, restart=30)
+    assert r.converged.all()
+    assert rel(r.x.cpu().numpy(), u) < 1e-7
+
+
+def test_longest_restart():
+    """restart = 200 (the maximum): one cycle reaches the tolerance; a
+    restart of 4 needs several cycles; both match the direct solution."""
+    need_gpu()
+    w = wl.small_random((16, 15, 14), npml=3, q=60.0, nsrc=3, seed=32, parts=(2, 2, 2))
+    say("restart 200")
+    F = oracle_fields(w)
+    b = op.point_sources(F, w.sources)
+    u = direct.solve(op.assemble(F), F.shape, b)
+    S = setup(w, prec=2, parts=w.parts)
+    r200 = S.solve(to_dev(b, S), 1e-10, restart=200, maxit=200)
+    assert r200.converged.all() and r200.cycles == 1
+    r4 = S.solve(to_dev(b, S), 1e-10, restart=4, maxit=400)
+    assert r4.converged.all() and r4.cycles > 1
+    assert rel(r200.x.cpu().numpy(), u) < 1e-7
+    assert rel(r4.x.cpu().numpy(), u) < 1e-7
+
+
+@pytest.mark.parametrize("prec", [2, 1])
+def test_largest_subdomain_plane(prec):
+    """One subdomain whose planes hold 128 x 64 = 8192 nodes (the largest
+    accepted): ORAS with a single subdomain is A^{-1} (sec. 2.1), so
+    A M^{-1} b = b checks the whole factorisation and substitution; one
+    FGMRES step solves.  One more column per plane is refused."""
+    need_gpu()
+    from paper_2110_15113_amd import oras
+    w = wl.small_random((128, 64, 6), npml=2, q=80.0, nsrc=2, seed=33, parts=(1, 1, 1), overlap=0)
+    say(f"plane of 8192 nodes, prec {prec}")
+    S = setup(w, prec=prec, parts=(1, 1, 1), overlap=0)
+    b = S.point_sources(w.sources)
+    y = S.apply_M(b)
+    r = b - S.apply_A(y, prec=oras.C128)
+    res = float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(b))
+    assert res < (1e-10 if prec == 2 else 1e-3), res
+    sol = S.solve(b, 1e-6 if prec == 1 else 1e-10)
+    assert sol.converged.all() and sol.total_iters <= (6 if prec == 1 else 1), sol.total_iters
+    S.close()
+    w2 = wl.small_random((129, 64, 6), npml=2, seed=33, parts=(1, 1, 1), overlap=0)
+    S2 = setup(w2, prec=prec)
+    with pytest.raises(oras.OrasError, match="8192"):
+        S2.factor((1, 1, 1), 0, prec)
+
+
+@pytest.mark.parametrize("parts,ov", [((6, 1, 2), 0), ((2, 2, 2), 0), ((6, 5, 4), 1)])
+def test_thin_boxes_and_zero_overlap(parts, ov):
+    """Boxes two nodes wide and overlap 0 (block Jacobi with Robin faces):
+    ORAS apply against the oracle in both precisions."""
+    need_gpu()
+    w = wl.small_random((12, 10, 8), npml=2, q=90.0, seed=34, parts=parts, overlap=ov)
+    say(f"thin boxes {parts} overlap {ov}")
+    F = oracle_fields(w)
+    x = rand_field((w.nz, w.ny, w.nx), 5, 19)
+    ref = ooras.ORAS(F, parts, ov).apply(x)
+    S = setup(w, prec=2, parts=parts, overlap=ov)
+    assert rel(S.apply_M(to_dev(x, S)).cpu().numpy(), ref) < 1e-9
+    S32 = setup(w, prec=1, parts=parts, overlap=ov)
+    assert rel(S32.apply_M(to_dev(x, S32)).cpu().numpy(), ref) < 1e-3
