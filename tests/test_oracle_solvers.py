@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 import scipy.sparse.linalg as spla
 
-from oracle import direct, krylov, operator as op, oras, stencil_table as st
+from oracle import direct, krylov, metrics, operator as op, oras, stencil_table as st
 from paper_2110_15113_amd import workloads as wl
 
 
@@ -79,6 +79,9 @@ def test_greens_function_homogeneous(Q):
     m = phys & (r >= 4 * h)
     rel = np.abs(u * mu - g)[m] / np.abs(g)[m]
     assert rel.max() < 1e-2, rel.max()
+    # the paper's error measure over the physical region (gain r, mute 4 h)
+    e = metrics.err(g, u * mu, (16, 16, 16), h, mute=4.0, region=phys)
+    assert e < 1e-2, e
 
 
 def test_oras_one_subdomain_is_exact():
