@@ -391,16 +391,18 @@ gj_colpanel_kernel(const SubDesc* subs, int k, int kb0, C<R>* fac) {
 }
 
 // A_IJ <- A_IJ - A_Ik A_kJ (I, J outside the pivot block): one wave per tile.
-// The tile A_IJ is read into registers first; for each pivot tile u the
-// operand tiles A_Iu, A_uJ are staged in LDS (one wait for memory per pair).
+// For each pivot tile u the tile A_uJ is staged in LDS and A_Iu is read from
+// memory directly as the row operand; the tile A_IJ is read after the
+// products.  One 8 KB LDS tile and few live registers let five waves share a
+// SIMD (with both operands staged and A_IJ held through the loop, two).
 // Work-group ids are mapped so that all tiles of one subdomain run on the same
 // XCD and read the pivot row and column panels from its L2.
 constexpr int NXCD = 8;
 template <typename R>
-__global__ void __launch_bounds__(64) gj_update_kernel(const SubDesc* subs, int nsub, int max_nt,
-                                                       int k, int kb0, C<R>* fac) {
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3)))
+gj_update_kernel(const SubDesc* subs, int nsub, int max_nt, int k, int kb0, C<R>* fac) {
   using T = C<R>;
-  __shared__ __align__(16) T sX[1024], sY[1024];
+  __shared__ __align__(16) T sY[1024];
   const int bid = blockIdx.x, r = bid / NXCD, items = max_nt * max_nt;
   const int sub = (r / items) * NXCD + bid % NXCD, item = r % items;
   if (sub >= nsub) return;
@@ -413,17 +415,16 @@ __global__ void __launch_bounds__(64) gj_update_kernel(const SubDesc* subs, int 
   R* Cr = reinterpret_cast<R*>(base + tile_off(I, J, sd.nt));
   TileMma<R> mm;
   mm.zero();
+  for (int u = 0; u < nb; ++u) {
+    tile_to_lds(base + tile_off(kb0 + u, J, sd.nt), sY);
+    __syncthreads();
+    mm.mac(base + tile_off(I, kb0 + u, sd.nt), sY);
+    __syncthreads();
+  }
   R cv[32];
   {
     int n = 0;
     mm.visit([&](int row, int col, int part, R) { cv[n++] = Cr[comp_of(row, col, part)]; });
-  }
-  for (int u = 0; u < nb; ++u) {
-    tile_to_lds(base + tile_off(I, kb0 + u, sd.nt), sX);
-    tile_to_lds(base + tile_off(kb0 + u, J, sd.nt), sY);
-    __syncthreads();
-    mm.mac(sX, sY);
-    __syncthreads();
   }
   int n = 0;
   mm.visit([&](int row, int col, int part, R v) {

@@ -202,10 +202,12 @@ plane_rhs_f32_kernel(const SubDesc* __restrict__ subs, int nsub, int nrb, int nc
 // wave).  A row of the factor tile layout holds, for each 4-k slice, rows
 // r = lane % 32 with entries 2 h, 2 h + 1 (h = lane / 32) in one float4; the
 // matching t operands come from the float4 of the operand-order layout.  The
-// next 32-k tile of both operands is prefetched into registers while the
-// current one feeds 16 NB instructions.
+// operands advance by half tiles of 16 k: the next half tile of both is
+// prefetched into registers while the current one feeds 8 NB instructions.
+// The half-tile buffers keep the wave within 168 registers, so three waves
+// share a SIMD (whole 32-k tiles took 202 registers and allowed two).
 template <typename Z, int NB>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3)))
 plane_gemm_f32_kernel(const SubDesc* __restrict__ subs, int nsub, int max_nt, int ncg, int cb0,
                       int k, int bwd, const float2* __restrict__ fac,
                       const float4* __restrict__ tvm, float2* __restrict__ ybuf,
@@ -236,33 +238,35 @@ plane_gemm_f32_kernel(const SubDesc* __restrict__ subs, int nsub, int max_nt, in
       acc[b][0][j] = 0.f;
       acc[b][1][j] = 0.f;
     }
-  float4 sa[8], sb[4][NB];
+  // half tiles of 16 k: 4 float4 of A and 2 x NB float4 of t per lane
+  float4 sa[4], sb[2][NB];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) sa[q] = A4[q * 64 + aoff];
+  for (int q = 0; q < 4; ++q) sa[q] = A4[q * 64 + aoff];
 #pragma unroll
-  for (int gg = 0; gg < 4; ++gg)
+  for (int gg = 0; gg < 2; ++gg)
 #pragma unroll
     for (int b = 0; b < NB; ++b) sb[gg][b] = B4[((long long)b * G + gg) * 64 + lane];
 
-  for (int J = 0; J < nt; ++J) {
-    float4 ca[8], cbv[4][NB];
+  for (int HJ = 0; HJ < 2 * nt; ++HJ) {
+    float4 ca[4], cbv[2][NB];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) ca[q] = sa[q];
+    for (int q = 0; q < 4; ++q) ca[q] = sa[q];
 #pragma unroll
-    for (int gg = 0; gg < 4; ++gg)
+    for (int gg = 0; gg < 2; ++gg)
 #pragma unroll
       for (int b = 0; b < NB; ++b) cbv[gg][b] = sb[gg][b];
-    if (J + 1 < nt) {
+    if (HJ + 1 < 2 * nt) {
+      const int J1 = (HJ + 1) >> 1, h1 = (HJ + 1) & 1;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) sa[q] = A4[(long long)(J + 1) * 512 + q * 64 + aoff];
+      for (int q = 0; q < 4; ++q) sa[q] = A4[(long long)J1 * 512 + (4 * h1 + q) * 64 + aoff];
 #pragma unroll
-      for (int gg = 0; gg < 4; ++gg)
+      for (int gg = 0; gg < 2; ++gg)
 #pragma unroll
         for (int b = 0; b < NB; ++b)
-          sb[gg][b] = B4[((long long)b * G + 4 * (J + 1) + gg) * 64 + lane];
+          sb[gg][b] = B4[((long long)b * G + 4 * J1 + 2 * h1 + gg) * 64 + lane];
     }
 #pragma unroll
-    for (int gg = 0; gg < 4; ++gg)
+    for (int gg = 0; gg < 2; ++gg)
 #pragma unroll
       for (int p = 0; p < 2; ++p) {
         const float4 a = ca[2 * gg + p];

@@ -1149,6 +1149,11 @@ oras_status oras_solve(oras_ctx c, const void* b_dev, void* x_dev, int nrhs, dou
   {
     double need = 0;
     if (!c->V.p || c->ws_s < s || c->ws_m < m) need += (double)ns * ((m + 1) * 16.0 + m * zsz + 2 * 16.0);
+    if (convert) {
+      const DevBuf& tb = kprec == ORAS_C64 ? c->Tmp64 : c->Tmp;
+      const size_t tbytes = (size_t)ns * (kprec == ORAS_C64 ? sizeof(float2) : sizeof(double2));
+      if (tb.bytes < tbytes) need += (double)tbytes;
+    }
     TRY(check_free(c, need));
   }
   if (convert) {
