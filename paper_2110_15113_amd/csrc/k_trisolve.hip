@@ -442,14 +442,17 @@ plane_gemm_f64_kernel(const SubDesc* __restrict__ subs, int nsub, int max_nt, in
     }
 }
 
-// Columns in chunks of at most 64 right-hand sides (8 groups of 8).
+// Columns in chunks of at most 32 right-hand sides (4 groups of 8).  The
+// accumulators of 4 groups keep a wave at 138 registers (three waves per
+// SIMD); 8 groups took 265 and one wave, and re-reading the factors for a
+// second chunk costs less than that (64 RHS: 111 -> 101 ms per FP64 apply).
 void gemm_f64_dispatch(const OrasPlan& pl, int k, int bwd, const double2* fac,
                        const double2* tvbuf, double2* ybuf, double2* z, int nx, int ny, int s,
                        hipStream_t st) {
   const int nsub8 = (pl.nsub + NXCD - 1) / NXCD * NXCD;
   const dim3 grid((unsigned)(nsub8 * pl.max_nt));
-  for (int c0 = 0; c0 < s; c0 += 8 * RHS_ALIGN) {
-    const int groups = std::min(8, (s - c0) / RHS_ALIGN);
+  for (int c0 = 0; c0 < s; c0 += 4 * RHS_ALIGN) {
+    const int groups = std::min(4, (s - c0) / RHS_ALIGN);
 #define ORAS_GEMM(NS_)                                                                           \
   hipLaunchKernelGGL((plane_gemm_f64_kernel<NS_>), grid, dim3(64), 0, st, pl.subs, pl.nsub,     \
                      pl.max_nt, k, bwd, fac, tvbuf, ybuf, z, nx, ny, s, c0)
@@ -457,11 +460,7 @@ void gemm_f64_dispatch(const OrasPlan& pl, int k, int bwd, const double2* fac,
       case 1: ORAS_GEMM(1); break;
       case 2: ORAS_GEMM(2); break;
       case 3: ORAS_GEMM(3); break;
-      case 4: ORAS_GEMM(4); break;
-      case 5: ORAS_GEMM(5); break;
-      case 6: ORAS_GEMM(6); break;
-      case 7: ORAS_GEMM(7); break;
-      default: ORAS_GEMM(8); break;
+      default: ORAS_GEMM(4); break;
     }
 #undef ORAS_GEMM
   }
