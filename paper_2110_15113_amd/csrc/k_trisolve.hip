@@ -370,18 +370,20 @@ __global__ void plane_rhs_f64_kernel(const SubDesc* __restrict__ subs, int k, in
 
 // Y_k (=|-=) S_k^{-1} t for one 32-row tile and 8 NS columns (one wave); a
 // 16-row x 8-column x 4-k step is two instructions (real and imaginary A).
+// Column group cg of the launch starts at column c0base + 8 NS cg.
 template <int NS>
 __global__ void __launch_bounds__(64)
-plane_gemm_f64_kernel(const SubDesc* __restrict__ subs, int nsub, int max_nt, int k, int bwd,
-                      const double2* __restrict__ fac, const double2* __restrict__ tvbuf,
+plane_gemm_f64_kernel(const SubDesc* __restrict__ subs, int nsub, int max_nt, int ncg, int k,
+                      int bwd, const double2* __restrict__ fac, const double2* __restrict__ tvbuf,
                       double2* __restrict__ ybuf, double2* __restrict__ z, int nx, int ny, int s,
-                      int c0) {
-  int sub, I;
-  xcd_map(max_nt, sub, I);
+                      int c0base) {
+  int sub, item;
+  xcd_map(max_nt * ncg, sub, item);
   if (sub >= nsub) return;
   const SubDesc sd = subs[sub];
   if (!plane_active(sd, k, bwd)) return;
   const int nt = sd.nt;
+  const int I = item / ncg, c0 = c0base + 8 * NS * (item % ncg);
   if (I >= nt) return;
   const int P = sd.P;
   const double2* A = fac + sd.fac_off + (long long)k * P * P + (long long)I * nt * (TILE * TILE);
@@ -442,28 +444,38 @@ plane_gemm_f64_kernel(const SubDesc* __restrict__ subs, int nsub, int max_nt, in
     }
 }
 
-// Columns in chunks of at most 32 right-hand sides (4 groups of 8).  The
-// accumulators of 4 groups keep a wave at 138 registers (three waves per
-// SIMD); 8 groups took 265 and one wave, and re-reading the factors for a
-// second chunk costs less than that (64 RHS: 111 -> 101 ms per FP64 apply).
+// Columns in groups of 8, at most 4 groups per wave: the accumulators of 4
+// keep a wave at 138 registers (three waves per SIMD; 8 groups took 265 and
+// one wave, and re-reading the factors costs less than that).  Fewer groups
+// per wave when a plane step would otherwise launch fewer than 2048 waves
+// (few or small subdomains): every column group is a work-group of the same
+// launch, and the groups of one row tile share its factor rows in L2.  (On
+// 64 subdomains of 28^2-node planes and 32 RHS, 2 groups per wave took
+// 14.6 ms per apply, 1 group 15.7 ms, 4 groups 19.1 ms.)  A remainder of
+// groups goes to a second launch.
 void gemm_f64_dispatch(const OrasPlan& pl, int k, int bwd, const double2* fac,
                        const double2* tvbuf, double2* ybuf, double2* z, int nx, int ny, int s,
                        hipStream_t st) {
   const int nsub8 = (pl.nsub + NXCD - 1) / NXCD * NXCD;
-  const dim3 grid((unsigned)(nsub8 * pl.max_nt));
-  for (int c0 = 0; c0 < s; c0 += 4 * RHS_ALIGN) {
-    const int groups = std::min(4, (s - c0) / RHS_ALIGN);
+  const int groups = s / RHS_ALIGN;
+  int ns = 4;
+  while (ns > 1 && (long long)nsub8 * pl.max_nt * (groups / ns) < 2048) ns >>= 1;
+  const int full = groups / ns, rem = groups % ns;
+  auto launch = [&](int nsw, int ncg, int c0base) {
+    const dim3 grid((unsigned)(nsub8 * pl.max_nt * ncg));
 #define ORAS_GEMM(NS_)                                                                           \
   hipLaunchKernelGGL((plane_gemm_f64_kernel<NS_>), grid, dim3(64), 0, st, pl.subs, pl.nsub,     \
-                     pl.max_nt, k, bwd, fac, tvbuf, ybuf, z, nx, ny, s, c0)
-    switch (groups) {
+                     pl.max_nt, ncg, k, bwd, fac, tvbuf, ybuf, z, nx, ny, s, c0base)
+    switch (nsw) {
       case 1: ORAS_GEMM(1); break;
       case 2: ORAS_GEMM(2); break;
       case 3: ORAS_GEMM(3); break;
       default: ORAS_GEMM(4); break;
     }
 #undef ORAS_GEMM
-  }
+  };
+  if (full > 0) launch(ns, full, 0);
+  if (rem > 0) launch(rem, 1, full * ns * RHS_ALIGN);
 }
 
 template <typename Z>
