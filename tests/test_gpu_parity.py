@@ -186,3 +186,32 @@ def test_exact_gradient_needs_weights_that_follow_m():
         S.gradient(U, U, weights=True)
     S.set_m(to_dev(1.01 / w.vel ** 2, S), weights="follow")
     S.gradient(U, U, weights=True)
+
+
+def test_free_surface_assembly_and_solve():
+    """Free-surface top (no PML on the low z side, Dirichlet ghost layer):
+    coefficients against the oracle's, and an FP64 ORAS-FGMRES solve against
+    the oracle's direct solution."""
+    need_gpu()
+    from oracle import direct
+    from paper_2110_15113_amd import oras
+    w = wl.small_random((15, 14, 13), npml=3, q=70.0, nsrc=2, seed=23, parts=(2, 2, 2))
+    say("free surface")
+    F = op.make_fields(w.vel, w.Q, w.omega, w.h, w.npml, free_surface=True)
+    S = oras.Solver(0)
+    dev = S.device
+    S.assemble(torch.as_tensor(w.vel, device=dev), w.h, w.npml, w.omega,
+               torch.as_tensor(w.Q, device=dev), prec=oras.C128, free_surface=True)
+    got = S.coefficients().cpu().numpy()
+    ref = op.row_coeffs(F)
+    assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
+    # the flag changes the top rows only
+    ref_pml = op.row_coeffs(oracle_fields(w))
+    diff = np.abs(ref - ref_pml).max(axis=(0, 2, 3))      # per z-plane (27, nz, ny, nx)
+    assert diff[0] > 0 and not diff[w.npml + 1:].any()
+    S.factor(w.parts, w.overlap, oras.C128)
+    b = op.point_sources(F, w.sources)
+    u = direct.solve(op.assemble(F), F.shape, b)
+    r = S.solve(to_dev(b, S), 1e-10)
+    assert r.converged.all()
+    assert rel(r.x.cpu().numpy(), u) < 1e-7

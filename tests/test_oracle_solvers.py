@@ -84,6 +84,39 @@ def test_greens_function_homogeneous(Q):
     assert e < 1e-2, e
 
 
+
+def test_free_surface_image_source():
+    """Free-surface top (Dirichlet ghost layer at k = -1, no top PML): in a
+    homogeneous medium the field is the free-space Green's function minus
+    that of the source mirrored about the ghost plane (k' = -2 - k_s), the
+    discrete operator being symmetric in z.  Errors are measured against the
+    amplitude of the direct wave; without the image term they are O(1)."""
+    n, c, h, f, npml, ks = 32, 2000.0, 25.0, 10.0, 8, 4
+    vel = np.full((n, n, n), c)
+    F = op.make_fields(vel, None, 2 * np.pi * f, h, npml, free_surface=True)
+    A = op.assemble(F)
+    b = op.point_sources(F, [(16, 16, ks)])[0]
+    M = oras.ORAS(F, (2, 2, 2), 2)
+    u, it, ok, _ = krylov.fgmres(lambda v: A @ v,
+                                 lambda v: M.apply(v.reshape(F.shape)).reshape(-1),
+                                 b.reshape(-1), 1e-10, 30, 300)
+    assert ok
+    u = u.reshape(F.shape)
+    kk, jj, ii = np.meshgrid(*[np.arange(n)] * 3, indexing="ij")
+    r = h * np.sqrt((ii - 16) ** 2 + (jj - 16) ** 2 + (kk - ks) ** 2)
+    ri = h * np.sqrt((ii - 16) ** 2 + (jj - 16) ** 2 + (kk + 2 + ks) ** 2)
+    k = 2 * np.pi * f / c
+    rr = np.maximum(r, h)
+    direct_wave = -h ** 3 * np.exp(1j * k * rr) / (4 * np.pi * rr)
+    g = direct_wave + h ** 3 * np.exp(1j * k * ri) / (4 * np.pi * ri)
+    _, mu = st.lam_mu(F.w[ks, 16, 16], (2 * np.pi * f / c * h) * np.array([1.0, 0.0, 0.0]))
+    m = ((ii >= npml) & (ii < n - npml) & (jj >= npml) & (jj < n - npml) & (kk < n - npml)
+         & (r >= 4 * h))
+    amp = np.abs(direct_wave)[m]
+    err = np.abs(u * mu - g)[m] / amp
+    assert err.max() < 1e-2, err.max()
+    assert (np.abs(u * mu - direct_wave)[m] / amp).max() > 0.5
+
 def test_oras_one_subdomain_is_exact():
     w = wl.small_random((10, 11, 12), npml=2, q=90)
     F = _fields(w)
