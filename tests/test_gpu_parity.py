@@ -215,3 +215,24 @@ def test_free_surface_assembly_and_solve():
     r = S.solve(to_dev(b, S), 1e-10)
     assert r.converged.all()
     assert rel(r.x.cpu().numpy(), u) < 1e-7
+
+
+@pytest.mark.parametrize("R0,power,c_ref", [(1e-2, 3, 3500.0), (1e-4, 1, 0.0)])
+def test_pml_parameters(R0, power, c_ref):
+    """PML law parameters of the assembly (reflection R0, profile power, and a
+    reference velocity; c_ref <= 0 takes the model maximum) against the
+    oracle's coefficients."""
+    need_gpu()
+    from paper_2110_15113_amd import oras
+    w = wl.small_random((13, 12, 11), npml=3, q=50.0, seed=24)
+    say(f"pml R0={R0} power={power} c_ref={c_ref}")
+    F = op.make_fields(w.vel, w.Q, w.omega, w.h, w.npml, R0=R0, power=power,
+                       c_ref=None if c_ref <= 0 else c_ref)
+    S = oras.Solver(0)
+    dev = S.device
+    S.assemble(torch.as_tensor(w.vel, device=dev), w.h, w.npml, w.omega,
+               torch.as_tensor(w.Q, device=dev), prec=oras.C128, R0=R0, power=power, c_ref=c_ref)
+    got = S.coefficients().cpu().numpy()
+    ref = op.row_coeffs(F)
+    assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
+    assert np.abs(ref - op.row_coeffs(oracle_fields(w))).max() > 1e-3 * np.abs(ref).max()
