@@ -928,7 +928,17 @@ oras_status oras_compress_factors(oras_ctx c, double eps, int pmax, oras_blr_inf
         it.nseg = nseg;
         it.a_off = store;
         it.list_off = loff;
-        eit[k].push_back(it);
+        if (c->factor_prec == ORAS_C64 && bsz[I] > 32) {
+          // complex64 expansion runs 32 rows per wave: two items per patch
+          BlrItem it2 = it;
+          it.rows = 32;
+          it2.row0 = 32;
+          it2.rows = bsz[I] - 32;
+          eit[k].push_back(it);
+          eit[k].push_back(it2);
+        } else {
+          eit[k].push_back(it);
+        }
         for (int J = 0; J < np; ++J) {
           BlrBlock& x = blocks[(size_t)(base + (long long)I * np + J)];
           x.rank = J == I ? -1 : rk(I, J);
