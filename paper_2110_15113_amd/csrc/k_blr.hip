@@ -353,10 +353,10 @@ __device__ inline bool item_map(int nitems, int ncg, int& it, int& cg) {
 }
 
 // Complex FP32: 32x32x2 MFMA, RT tiles of 32 rows x 32 columns per wave.
-// Expansion items take 32 rows (a row patch of more than 32 nodes is two
-// items, the second from row0 = 32): with one tile the wave needs 132
-// registers and three share a SIMD, where two tiles took 224 and two waves
-// (117 against 129 us per plane step on 160^3, 32 RHS).
+// Expansion items take 32 rows in both precisions (a row patch of more than
+// 32 nodes is two items, the second from row0 = 32): with one tile the wave
+// needs 132 registers and three share a SIMD, where two tiles took 224 and
+// two waves (117 against 129 us per plane step on 160^3, 32 RHS).
 // Operand row kk of the item is operand-buffer row rbase + (kk - 4 kq) for the
 // 4-row group kq; projection items read the patch's t rows, expansion items
 // walk their segments.
@@ -649,7 +649,7 @@ blr_gemm_f64_kernel(const SubDesc* __restrict__ subs, const BlrSub* __restrict__
   for (int rg = 0; rg < RG; ++rg)
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      const int l = 16 * rg + kk + 4 * t;
+      const int l = item.row0 + 16 * rg + kk + 4 * t;
       if (l >= bsz) continue;
       const int qx = x0 + l % w, qy = y0 + l / w;
       double* yr = Yk + (long long)(qy * sd.sx + qx) * 2 * s;
@@ -712,7 +712,7 @@ template <> struct BlrStep<double, double2> {
                          dim3(64), 0, st, pl.subs, pl.bsubs, pl.items + pl.p_first[k],
                          pl.p_count[k], ncg, k, bwd, astore, pl.lists, bt, ybuf, z, nx, ny, s,
                          s16);
-    hipLaunchKernelGGL((blr_gemm_f64_kernel<4, 1>), dim3((unsigned)(pl.e_count[k] * ncg)),
+    hipLaunchKernelGGL((blr_gemm_f64_kernel<2, 1>), dim3((unsigned)(pl.e_count[k] * ncg)),
                        dim3(64), 0, st, pl.subs, pl.bsubs, pl.items + pl.e_first[k],
                        pl.e_count[k], ncg, k, bwd, astore, pl.lists, bt, ybuf, z, nx, ny, s, s16);
     if (ev) (void)hipEventRecord(ev[1], st);

@@ -928,8 +928,8 @@ oras_status oras_compress_factors(oras_ctx c, double eps, int pmax, oras_blr_inf
         it.nseg = nseg;
         it.a_off = store;
         it.list_off = loff;
-        if (c->factor_prec == ORAS_C64 && bsz[I] > 32) {
-          // complex64 expansion runs 32 rows per wave: two items per patch
+        if (bsz[I] > 32) {
+          // the expansion runs 32 rows per wave: two items per patch
           BlrItem it2 = it;
           it.rows = 32;
           it2.row0 = 32;
