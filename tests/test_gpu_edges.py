@@ -1,6 +1,7 @@
 """Edge cases of the GPU path at the limits the library accepts: the widest
 right-hand-side block (256 columns), the longest restart (200), the largest
-subdomain plane (8192 nodes), the thinnest boxes (2 nodes) and zero overlap."""
+subdomain plane (8192 nodes), the thinnest boxes (2 nodes), zero overlap and
+the smallest grid (3 nodes per axis)."""
 import numpy as np
 import pytest
 import torch
@@ -95,3 +96,28 @@ def test_thin_boxes_and_zero_overlap(parts, ov):
     assert rel(S.apply_M(to_dev(x, S)).cpu().numpy(), ref) < 1e-9
     S32 = setup(w, prec=1, parts=parts, overlap=ov)
     assert rel(S32.apply_M(to_dev(x, S32)).cpu().numpy(), ref) < 1e-3
+
+
+@pytest.mark.parametrize("prec", [2, 1])
+def test_smallest_grid(prec):
+    """The smallest accepted grid (3 nodes per axis, one PML layer, so one
+    physical node) as one subdomain, and with npml = 0 split 1 x 1 x 1: the
+    solve against the oracle's direct solution."""
+    need_gpu()
+    from paper_2110_15113_amd import oras
+    for npml in (1, 0):
+        vel = np.full((3, 3, 3), 2000.0)
+        vel[1, 1, 2] = 2500.0
+        Q = np.full_like(vel, 80.0)
+        F = op.make_fields(vel, Q, 2 * np.pi * 5.0, 25.0, npml)
+        b = op.point_sources(F, [(1, 1, 1)])
+        u = direct.solve(op.assemble(F), F.shape, b)
+        S = oras.Solver(0)
+        dev = S.device
+        S.assemble(torch.as_tensor(vel, device=dev), 25.0, npml, 2 * np.pi * 5.0,
+                   torch.as_tensor(Q, device=dev), prec=prec)
+        S.factor((1, 1, 1), 0, prec)
+        r = S.solve(to_dev(b, S), 1e-6 if prec == 1 else 1e-12)
+        assert r.converged.all()
+        assert rel(r.x.cpu().numpy(), u) < (1e-5 if prec == 1 else 1e-11), (npml, prec)
+        S.close()
