@@ -117,13 +117,15 @@ __device__ inline C<R> plane_rhs_entry(const SubDesc& sd, int k, int bwd, int q,
 // component 2 p + e is part (rr & 1) of t[8 g + 4 p + 2 h + e][16 cb + rr / 2]
 // (zero beyond the plane or beyond column s).
 //
-// A work-group forms t for 16 plane rows (two groups of 8) and 32 columns (two
-// column blocks).  Sixteen lanes share a row, two columns each, so every
+// A work-group forms t for 32 plane rows (four groups of 8) and 32 columns
+// (two column blocks).  Eight lanes share a row, four columns each, so every
 // vector load of y or v covers whole cache lines of one row and a coupling
-// coefficient is one broadcast per row; the tile is transposed through LDS and
-// written out as whole float4 operands, one per thread.
-constexpr int RB_ROWS = 16;
-constexpr int RB_THREADS = RB_ROWS * 16;
+// coefficient is one broadcast per row, loaded once per four columns (with
+// sixteen lanes of two columns: 63.2 against 61.9 us per plane step on 160^3,
+// 32 RHS); the tile is transposed through LDS and written out as whole float4
+// operands, two per thread.
+constexpr int RB_ROWS = 32;
+constexpr int RB_THREADS = RB_ROWS * 8;
 
 __global__ void __launch_bounds__(RB_THREADS)
 plane_rhs_f32_kernel(const SubDesc* __restrict__ subs, int nsub, int nrb, int ncc, int k, int bwd,
@@ -137,22 +139,26 @@ plane_rhs_f32_kernel(const SubDesc* __restrict__ subs, int nsub, int nrb, int nc
   const SubDesc sd = subs[sub];
   if (!plane_active(sd, k, bwd)) return;
   const int G = sd.P / 8;
-  const int cc = item / nrb, g0 = 2 * (item % nrb);
+  const int cc = item / nrb, g0 = 4 * (item % nrb);
   if (g0 >= G) return;
 
   const int tid = threadIdx.x;
-  const int rl = tid >> 4, cp = tid & 15;
+  const int rl = tid >> 3, cp = tid & 7;
   const int q = 8 * g0 + rl;
-  const int c = 32 * cc + 2 * cp;
-  float2 t0 = make_float2(0.f, 0.f), t1 = make_float2(0.f, 0.f);
+  const int c = 32 * cc + 4 * cp;
+  float2 t[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) t[j] = make_float2(0.f, 0.f);
   if (q < sd.p && c < s) {
     const int qx = q % sd.sx, qy = q / sd.sx;
     if (!bwd) {
       const long long gn = ((long long)(sd.lo[2] + k) * ny + sd.lo[1] + qy) * nx + sd.lo[0] + qx;
-      const double2 v0 = v[gn * s + c], v1 = v[gn * s + c + 1];
-      const double s0 = scale ? scale[c] : 1.0, s1 = scale ? scale[c + 1] : 1.0;
-      t0 = make_float2((float)(v0.x * s0), (float)(v0.y * s0));
-      t1 = make_float2((float)(v1.x * s1), (float)(v1.y * s1));
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const double2 vj = v[gn * s + c + j];
+        const double sj = scale ? scale[c + j] : 1.0;
+        t[j] = make_float2((float)(vj.x * sj), (float)(vj.y * sj));
+      }
     }
     if (bwd || k > 0) {
       const long long nbox = (long long)sd.sx * sd.sy * sd.sz;
@@ -161,9 +167,6 @@ plane_rhs_f32_kernel(const SubDesc* __restrict__ subs, int nsub, int nrb, int nc
       const float2* Yn = ybuf + (sd.y_off + (long long)(bwd ? k + 1 : k - 1) * sd.P) * s + c;
       const int ez = bwd ? 1 : -1;
       const float sg = bwd ? 1.f : -1.f;
-      // couplings that leave the box are stored as exact zeros in the local
-      // coefficients (the restricted rows drop them), so clamped neighbour
-      // indices contribute nothing and the loads need no branches
 #pragma unroll
       for (int dy = -1; dy <= 1; ++dy) {
         const int py = min(max(qy + dy, 0), sd.sy - 1);
@@ -173,29 +176,36 @@ plane_rhs_f32_kernel(const SubDesc* __restrict__ subs, int nsub, int nrb, int nc
           float2 l = L[eidx(dx, dy, ez) * nbox + node];
           l.x *= sg;
           l.y *= sg;
-          const float4 y2 = *reinterpret_cast<const float4*>(Yn + (long long)(py * sd.sx + px) * s);
-          cfma(t0, l, make_float2(y2.x, y2.y));
-          cfma(t1, l, make_float2(y2.z, y2.w));
+          const float4* yp = reinterpret_cast<const float4*>(Yn + (long long)(py * sd.sx + px) * s);
+          const float4 y0 = yp[0], y1 = yp[1];
+          cfma(t[0], l, make_float2(y0.x, y0.y));
+          cfma(t[1], l, make_float2(y0.z, y0.w));
+          cfma(t[2], l, make_float2(y1.x, y1.y));
+          cfma(t[3], l, make_float2(y1.z, y1.w));
         }
       }
     }
   }
-  tile[rl][2 * cp] = t0;
-  tile[rl][2 * cp + 1] = t1;
-  __syncthreads();
-  // one float4 per thread: column block 2 cc + cbl, row group g0 + gl, lane
-  const int cbl = tid >> 7, gl = (tid >> 6) & 1, lane = tid & 63;
-  const int cb = 2 * cc + cbl;
-  if (cb >= s16 / 16 || g0 + gl >= G) return;
-  const int h = lane >> 5, rr = lane & 31, ci = 16 * cbl + (rr >> 1);
-  float val[4];
 #pragma unroll
-  for (int j4 = 0; j4 < 4; ++j4) {
-    const float2 w = tile[8 * gl + 4 * (j4 >> 1) + 2 * h + (j4 & 1)][ci];
-    val[j4] = (rr & 1) ? w.y : w.x;
+  for (int j = 0; j < 4; ++j) tile[rl][4 * cp + j] = t[j];
+  __syncthreads();
+  // two float4 per thread: column block 2 cc + cbl, row group g0 + gl, lane
+#pragma unroll
+  for (int o = 0; o < 2; ++o) {
+    const int idx = tid + RB_THREADS * o;
+    const int cbl = idx >> 8, gl = (idx >> 6) & 3, lane = idx & 63;
+    const int cb = 2 * cc + cbl;
+    if (cb >= s16 / 16 || g0 + gl >= G) continue;
+    const int h = lane >> 5, rr = lane & 31, ci = 16 * cbl + (rr >> 1);
+    float val[4];
+#pragma unroll
+    for (int j4 = 0; j4 < 4; ++j4) {
+      const float2 w = tile[8 * gl + 4 * (j4 >> 1) + 2 * h + (j4 & 1)][ci];
+      val[j4] = (rr & 1) ? w.y : w.x;
+    }
+    tvm[sd.tv_off * s16 / 2 + ((long long)cb * G + g0 + gl) * 64 + lane] =
+        make_float4(val[0], val[1], val[2], val[3]);
   }
-  tvm[sd.tv_off * s16 / 2 + ((long long)cb * G + g0 + gl) * 64 + lane] =
-      make_float4(val[0], val[1], val[2], val[3]);
 }
 
 // Y_k (=|-=) S_k^{-1} t for one 32-row tile and NB blocks of 16 columns (one
@@ -483,7 +493,7 @@ void plane_step_f32(const OrasPlan& pl, int k, int bwd, const float2* fac, const
                     float2* ybuf, float2* tvbuf, const double2* v, const double* scale, Z* z,
                     int nx, int ny, int s, hipStream_t st, hipEvent_t* ev) {
   const int s16 = (int)pad16(s);
-  const int nrb = (int)((pl.max_p + RB_ROWS - 1) / RB_ROWS);   // 16-row blocks
+  const int nrb = (int)((pl.max_p + RB_ROWS - 1) / RB_ROWS);   // 32-row blocks
   const int ncc = (s16 + 31) / 32;                               // 32-column chunks
   const int nsub8 = (pl.nsub + NXCD - 1) / NXCD * NXCD;
   hipLaunchKernelGGL(plane_rhs_f32_kernel, dim3((unsigned)(nsub8 * nrb * ncc)), dim3(RB_THREADS), 0,
