@@ -39,8 +39,11 @@ class FrequencyBatch:
         self.prec = prec
         self.items: List[FrequencyState] = []
         dev = torch.device("cuda", device)
+        self.device = dev
+        caller = torch.cuda.current_stream(dev)
         for om in omegas:
             st = torch.cuda.Stream(device=dev)           # default priority
+            st.wait_stream(caller)                        # vel and Q come from the caller's stream
             with torch.cuda.stream(st):
                 S = oras.Solver(device)
                 S.assemble(vel, h, npml, float(om), Q, prec=prec)
@@ -49,8 +52,14 @@ class FrequencyBatch:
 
     def _run(self, fn, concurrent: bool):
         """fn(i, state) for every frequency, on its stream; in one thread each
-        when concurrent.  Re-raises the first failure."""
+        when concurrent.  Each frequency's stream first waits for the work
+        queued so far on the caller's stream (its inputs may still be in
+        flight there), and is synchronised before this returns.  Re-raises
+        the first failure."""
         errors: List[BaseException] = []
+        caller = torch.cuda.current_stream(self.device)
+        for it in self.items:
+            it.stream.wait_stream(caller)
 
         def body(i, it):
             try:
