@@ -177,7 +177,12 @@ class SolveResult:
 
 
 class Solver:
-    """One library context: a grid, its operator, its subdomain factors."""
+    """One library context: a grid, its operator, its subdomain factors.
+
+    Every library call runs on the HIP stream that was current when the
+    Solver was created; tensors passed in must be ready in that stream's
+    order (made on it, or the stream made to wait for theirs), and the calls
+    that return host results synchronise with it."""
 
     def __init__(self, device: int = 0, host_only: bool = False):
         L = lib()
