@@ -236,3 +236,37 @@ def test_pml_parameters(R0, power, c_ref):
     ref = op.row_coeffs(F)
     assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
     assert np.abs(ref - op.row_coeffs(oracle_fields(w))).max() > 1e-3 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_gemm_accounting(prec):
+    """The per-launch accounting behind the plane-GEMM roofline: one launch
+    per plane step (2 max_sz - 1 per apply) and, per active subdomain plane,
+    8 p^2 nrhs flops and p^2 + (2 or 3) p nrhs complex entries, where the
+    backward sweep runs from the second-to-last plane down to the lowest
+    owned one; recomputed here from the oracle's partition."""
+    need_gpu()
+    w = wl.small_random((17, 15, 14), npml=2, q=60.0, seed=25, parts=(2, 2, 2), overlap=2)
+    say(f"gemm accounting prec={prec}")
+    S = setup(w, prec=prec, parts=w.parts)
+    nrhs = 5
+    x = rand_field((w.nz, w.ny, w.nx), nrhs, 13)
+    S.profile(True)
+    S.apply_M(to_dev(x, S))
+    secs, launches, flops, nbytes = S.kernel_stats()
+    subs = ooras.partition((w.nx, w.ny, w.nz), w.parts, w.overlap)
+    sz = [s.hi[2] - s.lo[2] for s in subs]
+    assert launches == 2 * max(sz) - 1
+    f = b = 0.0
+    cs = 8 if prec == 1 else 16
+    for s in subs:
+        p = (s.hi[0] - s.lo[0]) * (s.hi[1] - s.lo[1])
+        nz_ = s.hi[2] - s.lo[2]
+        for k in range(nz_):
+            f += 8.0 * p * p * nrhs
+            b += cs * (p * p + 2 * p * nrhs)
+            if k <= nz_ - 2 and k >= s.olo[2] - s.lo[2]:
+                f += 8.0 * p * p * nrhs
+                b += cs * (p * p + 3 * p * nrhs)
+    assert flops == f and nbytes == b, (flops, f, nbytes, b)
+    assert secs > 0
