@@ -33,9 +33,14 @@
  *     the Krylov workspace; they are freed by oras_destroy.
  *
  * Errors
- *   Every function returns an oras_status and never aborts.  Argument and
- *   state checks run before any device call; on error the context keeps its
- *   previous valid state and oras_last_error() describes the problem.
+ *   Every function returns an oras_status and never aborts; oras_last_error()
+ *   describes the problem.  Argument and state checks run before any device
+ *   call, and model arrays (velocity, Q, m) are checked on the device before
+ *   the context changes, so ORAS_E_ARG and ORAS_E_STATE leave the context in
+ *   its previous valid state.  A call that fails later (ORAS_E_OOM, ORAS_E_HIP,
+ *   ORAS_E_NUMERIC) may have dropped what it was replacing: the operator and
+ *   factors for oras_assemble and oras_set_m, the factors for
+ *   oras_factor_subdomains, the compressed form for oras_compress_factors.
  *
  * State machine: create -> assemble -> factor_subdomains -> solve ...
  *   assemble and set_m drop the factors (B_j depends on m).
@@ -133,8 +138,10 @@ const char* oras_last_error(oras_ctx ctx);
 oras_status oras_weight_table(double* out_host, int capacity, double* g0, double* dg, int* count);
 
 /* Assemble the operator (paper eq. 1; sec. 2.3 27-point lambda-adaptive
- * stencil; PML per sec. 3.1).  vel_dev: velocity (m/s, > 0, finite);
- * q_dev: quality factor (> 0) or NULL for no attenuation; omega > 0;
+ * stencil; PML per sec. 3.1).  vel_dev: velocity (m/s, every entry finite and
+ * > 0, else ORAS_E_ARG with the number of offending entries);
+ * q_dev: quality factor (every entry finite and > 0, same check) or NULL for
+ * no attenuation; omega > 0;
  * stencil_prec: ORAS_C128 (all FP64) or ORAS_C64 (the Krylov stencil runs in
  * complex FP32; an FP64 copy is kept for the true residual).  Requires
  * 3 <= nx, ny, nz, 0 <= 2 npml < min(n).  Drops any factors. */
@@ -142,7 +149,8 @@ oras_status oras_assemble(oras_ctx ctx, const oras_grid* grid, const double* vel
                           const double* q_dev, double omega, const oras_pml* pml,
                           int stencil_prec);
 
-/* Replace the real squared slowness m (s^2/m^2, (nz,ny,nx) float64 > 0) and
+/* Replace the real squared slowness m (s^2/m^2, (nz,ny,nx) float64, every
+ * entry finite and > 0, else ORAS_E_ARG with the context unchanged) and
  * re-assemble with the stencil weights, PML and Q frozen at the last
  * oras_assemble.  Used by the differentiable forward map.  Drops factors. */
 oras_status oras_set_m(oras_ctx ctx, const double* m_dev);
@@ -206,11 +214,18 @@ oras_status oras_point_sources(oras_ctx ctx, const int* idx_host, const double* 
                                int nrhs, void* b_dev);
 
 /* d_dev (nrhs, nrec) complex128 := u sampled at receivers rec_dev
- * (nrec x 3 int32 (i, j, k), device).  u_dev (nrhs, nz, ny, nx). */
+ * (nrec x 3 int32 (i, j, k), device).  u_dev (nrhs, nz, ny, nx).  This is the
+ * observation operator P of the receiver misfit that FWI minimises (sec. 1:
+ * the forward engine of frequency-domain FWI; sec. 4: many sources and
+ * receivers per frequency).  Receiver indices are copied to the host and
+ * checked against the grid first (ORAS_E_ARG). */
 oras_status oras_sample(oras_ctx ctx, const void* u_dev, int nrhs, const int* rec_dev, int nrec,
                         void* d_dev);
 
-/* b_dev (nrhs, nz, ny, nx) := P^T d (zero elsewhere, duplicates summed). */
+/* b_dev (nrhs, nz, ny, nx) := P^T d (zero elsewhere, duplicates summed): the
+ * adjoint of oras_sample, which carries the data residual back to the grid as
+ * the adjoint source of the FWI gradient (sec. 1, sec. 4).  Same receiver
+ * layout and checks as oras_sample. */
 oras_status oras_spread(oras_ctx ctx, const void* d_dev, int nrhs, const int* rec_dev, int nrec,
                         void* b_dev);
 
@@ -269,9 +284,13 @@ oras_status oras_blr_ranks(oras_ctx ctx, int sub, int plane, int* ranks_host, in
                            int* npatch);
 
 /* Test hooks running the same kernels as the solver.
- * oras_apply_A: y = A x in precision prec (ORAS_C64 needs stencil_prec C64).
- * oras_apply_M: y = M^{-1} x with the current factors.
- * x, y: (nrhs, nz, ny, nx) complex128. */
+ * oras_apply_A: y = A x, the 27-point operator of eq. 1.1 (sec. 2.3), in
+ *   precision prec (ORAS_C64 needs stencil_prec C64).
+ * oras_apply_M: y = M^{-1} x = sum_j R_j^T D_j B_j^{-1} R_j x, the one-level
+ *   ORAS preconditioner of sec. 2.1 with the local solves of sec. 2.2, with
+ *   the current factors.
+ * x, y: (nrhs, nz, ny, nx) complex128, 1 <= nrhs <= 256, device, caller-owned.
+ * Internal staging buffers are allocated by the context and kept. */
 oras_status oras_apply_A(oras_ctx ctx, const void* x_dev, void* y_dev, int nrhs, int prec);
 oras_status oras_apply_M(oras_ctx ctx, const void* x_dev, void* y_dev, int nrhs);
 

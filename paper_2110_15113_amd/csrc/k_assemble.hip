@@ -20,6 +20,7 @@
 // the point and f = 1/2 for the in-plane family (each axis lies in two
 // planes), 1 otherwise.
 #include <algorithm>
+#include <cfloat>
 
 #include "oras_internal.h"
 
@@ -319,35 +320,61 @@ __global__ void pml_kernel(double2* prof, int n, int npml, double h, double omeg
   prof[t] = make_double2(1.0, sigma / omega);
 }
 
-// Maximum of x in two fixed-order stages: MAXRED_BLOCKS partial maxima, then one
-// work-group over them (out[0]; out[1 ..] holds the partials).
-constexpr int MAXRED_BLOCKS = 1024;
-__global__ void max_partial_kernel(const double* x, long long n, double* part) {
+// Check of a model array in two fixed-order stages: per work-group the
+// maximum over the valid entries and the number of invalid ones (not finite,
+// or not above zero), then one work-group over the partials.  out[0] = the
+// maximum (-inf if no entry is valid), out[1] = the invalid count; the
+// partials follow (out[2 ..]).  A NaN fails every comparison, so it is
+// counted as invalid rather than dropped by the maximum.
+constexpr int CHECK_BLOCKS = 1024;
+__global__ void check_partial_kernel(const double* x, long long n, double* part) {
   __shared__ double red[256];
-  double m = -INFINITY;
+  __shared__ double cnt[256];
+  double m = -INFINITY, bad = 0.0;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x)
-    m = fmax(m, x[i]);
+       i += (long long)gridDim.x * blockDim.x) {
+    const double v = x[i];
+    if (v > 0.0 && v <= DBL_MAX) m = fmax(m, v);
+    else bad += 1.0;
+  }
   red[threadIdx.x] = m;
+  cnt[threadIdx.x] = bad;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    if (threadIdx.x < s) {
+      red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+      cnt[threadIdx.x] += cnt[threadIdx.x + s];
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = red[0];
+    part[2 * blockIdx.x + 1] = cnt[0];
+  }
 }
 
-__global__ void max_reduce_kernel(const double* part, int np, double* out) {
+__global__ void check_reduce_kernel(const double* part, int np, double* out) {
   __shared__ double red[256];
-  double m = -INFINITY;
-  for (int i = threadIdx.x; i < np; i += blockDim.x) m = fmax(m, part[i]);
+  __shared__ double cnt[256];
+  double m = -INFINITY, bad = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) {
+    m = fmax(m, part[2 * i]);
+    bad += part[2 * i + 1];
+  }
   red[threadIdx.x] = m;
+  cnt[threadIdx.x] = bad;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    if (threadIdx.x < s) {
+      red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+      cnt[threadIdx.x] += cnt[threadIdx.x + s];
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = red[0];
+  if (threadIdx.x == 0) {
+    out[0] = red[0];
+    out[1] = cnt[0];
+  }
 }
 
 }  // namespace
@@ -388,11 +415,12 @@ void launch_pml(double2* prof, int n, int npml, double h, double omega, double c
                      h, omega, c_ref, R0, power, low, high);
 }
 
-// out must hold 1 + MAXRED_BLOCKS doubles.
-void launch_max_reduce(const double* x, long long n, double* out, hipStream_t s) {
-  const int nb = (int)std::min<long long>(MAXRED_BLOCKS, std::max<long long>(1, (n + 255) / 256));
-  hipLaunchKernelGGL(max_partial_kernel, dim3(nb), dim3(256), 0, s, x, n, out + 1);
-  hipLaunchKernelGGL(max_reduce_kernel, dim3(1), dim3(256), 0, s, out + 1, nb, out);
+long long field_check_doubles() { return 2 + 2 * CHECK_BLOCKS; }
+
+void launch_field_check(const double* x, long long n, double* out, hipStream_t s) {
+  const int nb = (int)std::min<long long>(CHECK_BLOCKS, std::max<long long>(1, (n + 255) / 256));
+  hipLaunchKernelGGL(check_partial_kernel, dim3(nb), dim3(256), 0, s, x, n, out + 2);
+  hipLaunchKernelGGL(check_reduce_kernel, dim3(1), dim3(256), 0, s, out + 2, nb, out);
 }
 
 }  // namespace oras

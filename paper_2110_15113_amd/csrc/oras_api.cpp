@@ -195,6 +195,23 @@ oras_status check_free(oras_ctx c, double bytes) {
   return ORAS_OK;
 }
 
+// Checks a model array on the device before the context changes: every one of
+// its n entries must be finite and > 0.  max_out (may be null) receives the
+// largest entry.
+oras_status check_field(oras_ctx c, const double* x, long long n, const char* what,
+                        double* max_out) {
+  TRY(dev_alloc(c, c->scratch8, (size_t)field_check_doubles() * sizeof(double)));
+  launch_field_check(x, n, c->scratch8.as<double>(), c->stream);
+  double r[2] = {0.0, 0.0};
+  HIP_TRY(c, hipMemcpyAsync(r, c->scratch8.p, sizeof(r), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (r[1] > 0.0)
+    return fail(c, ORAS_E_ARG, std::string(what) + ": " + std::to_string((long long)r[1]) +
+                                   " entries are not finite and > 0");
+  if (max_out) *max_out = r[0];
+  return ORAS_OK;
+}
+
 OpView opview(oras_ctx c) {
   OpView v;
   v.nx = c->nx;
@@ -388,6 +405,39 @@ void interleave(const std::vector<BlrItem>& in, std::vector<BlrItem>& out, int& 
 
 }  // namespace
 
+namespace oras {
+
+oras_status check_apply_A(oras_ctx c, const void* x_dev, const void* y_dev, int nrhs, int prec) {
+  if (!c) return ORAS_E_ARG;
+  if (!x_dev || !y_dev) return fail(c, ORAS_E_ARG, "null vector");
+  if (nrhs < 1 || nrhs > 256) return fail(c, ORAS_E_ARG, "nrhs must be 1..256");
+  if (prec != ORAS_C64 && prec != ORAS_C128) return fail(c, ORAS_E_ARG, "bad precision");
+  if (!c->assembled) return fail(c, ORAS_E_STATE, "apply_A before assemble");
+  if (prec == ORAS_C64 && c->stencil_prec != ORAS_C64)
+    return fail(c, ORAS_E_STATE, "no complex64 stencil assembled");
+  return check_device(c);
+}
+
+oras_status apply_A_staged(oras_ctx c, const void* x_dev, void* y_dev, int nrhs, int prec,
+                           double2* xin, double2* yout, float2* x32) {
+  const long long s = pad_s(nrhs);
+  launch_to_internal((const double2*)x_dev, xin, c->n, nrhs, (int)s, 0, c->stream);
+  if (prec == ORAS_C64) {
+    launch_cast<float>(xin, x32, c->n * s, c->stream);
+    launch_stencil<float>(c->coef64.as<float2>(), x32, nullptr, yout, c->nx, c->ny, c->nz,
+                          (int)s, c->stream);
+  } else {
+    launch_stencil<double>(c->coef128.as<double2>(), xin, nullptr, yout, c->nx, c->ny, c->nz,
+                           (int)s, c->stream);
+  }
+  launch_from_internal(yout, (double2*)y_dev, c->n, nrhs, (int)s, 0, c->stream);
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return ORAS_OK;
+}
+
+}  // namespace oras
+
 extern "C" {
 
 oras_status oras_create(oras_ctx* out, int device, void* hip_stream) {
@@ -485,15 +535,21 @@ oras_status oras_assemble(oras_ctx c, const oras_grid* g, const double* vel_dev,
   TRY(check_device(c));
   const double t0 = now();
   const long long n = (long long)g->nx * g->ny * g->nz;
+  // model checks first: a rejected model leaves the context as it was
+  double vmax = 0;
+  TRY(check_field(c, vel_dev, n, "velocity", &vmax));
+  if (q_dev) TRY(check_field(c, q_dev, n, "Q", nullptr));
   const double need = (double)n * (7 * 8 + 16 * 2 + 27 * 16 + (stencil_prec == ORAS_C64 ? 27 * 8 : 0));
-  // buffers of an earlier assembly are reused when large enough
-  c->assembled = false;
-  c->factored = false;
   {
     const double held = (double)(c->w7.bytes + c->mt.bytes + c->qf.bytes + c->coef128.bytes +
                                  c->coef64.bytes);
     TRY(check_free(c, need - held));
   }
+  // buffers of an earlier assembly are reused when large enough; the factors
+  // (and their compressed form) belong to the old operator
+  c->assembled = false;
+  c->release_blr();
+  c->factored = false;
   c->nx = g->nx;
   c->ny = g->ny;
   c->nz = g->nz;
@@ -513,18 +569,8 @@ oras_status oras_assemble(oras_ctx c, const oras_grid* g, const double* vel_dev,
   TRY(dev_alloc(c, c->coef128, (size_t)n * 27 * sizeof(double2)));
   if (stencil_prec == ORAS_C64) TRY(dev_alloc(c, c->coef64, (size_t)n * 27 * sizeof(float2)));
   TRY(dev_alloc(c, c->wtab, t.w.size() * sizeof(double)));
-  TRY(dev_alloc(c, c->scratch8, (1 + 1024) * sizeof(double)));   // max + partial maxima
   HIP_TRY(c, hipMemcpyAsync(c->wtab.p, t.w.data(), t.w.size() * sizeof(double),
                             hipMemcpyHostToDevice, c->stream));
-  // velocity checks and the PML reference velocity (maximum of the model)
-  launch_max_reduce(vel_dev, n, c->scratch8.as<double>(), c->stream);
-  double vmax = 0;
-  HIP_TRY(c, hipMemcpyAsync(&vmax, c->scratch8.p, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
-  if (!finite_pos(vmax)) {
-    c->release_all();
-    return fail(c, ORAS_E_ARG, "velocity maximum is not finite and positive");
-  }
   c->c_ref = pml->c_ref > 0 ? pml->c_ref : vmax;
   launch_fields(vel_dev, q_dev, nullptr, c->wtab.as<double>(), t.count, t.g0, t.dg, c->nx, c->ny,
                 c->nz, c->h, omega, c->w7.as<double>(), c->qf.as<double2>(), c->mt.as<double2>(),
@@ -552,6 +598,7 @@ oras_status oras_set_m_ex(oras_ctx c, const double* m_dev, int flags) {
   if (flags & ~ORAS_WEIGHTS_FOLLOW_M) return fail(c, ORAS_E_ARG, "unknown set_m flags");
   if (!c->assembled) return fail(c, ORAS_E_STATE, "set_m before assemble");
   TRY(check_device(c));
+  TRY(check_field(c, m_dev, c->n, "m", nullptr));
   const Table& t = weight_table();
   c->release_factors();
   const bool follow = (flags & ORAS_WEIGHTS_FOLLOW_M) != 0;
@@ -650,11 +697,14 @@ oras_status oras_factor_subdomains_ex(oras_ctx c, const int parts[3], int overla
   const size_t cs = csize(factor_prec);
   const double need = (double)(fac_off + t_off + lca_off) * cs;
   TRY(check_device(c));
-  c->factored = false;
   {
     const double held = (double)(c->fac.bytes + c->tbuf.bytes + c->lca.bytes);
     TRY(check_free(c, need - held));
   }
+  // the old factors (and their compressed form) are dropped from here on; the
+  // buffers are reused when large enough
+  c->release_blr();
+  c->factored = false;
   DevBuf& tbuf = c->tbuf;
   TRY(dev_alloc(c, c->fac, (size_t)fac_off * cs));
   oras_status st = dev_alloc(c, tbuf, (size_t)t_off * cs);
@@ -1072,23 +1122,14 @@ oras_status oras_subdomain(oras_ctx c, int j, int* nsub, int* box12) {
 }
 
 oras_status oras_apply_A(oras_ctx c, const void* x_dev, void* y_dev, int nrhs, int prec) {
-  if (!c) return ORAS_E_ARG;
-  if (!x_dev || !y_dev) return fail(c, ORAS_E_ARG, "null vector");
-  if (nrhs < 1 || nrhs > 256) return fail(c, ORAS_E_ARG, "nrhs must be 1..256");
-  if (prec != ORAS_C64 && prec != ORAS_C128) return fail(c, ORAS_E_ARG, "bad precision");
-  if (!c->assembled) return fail(c, ORAS_E_STATE, "apply_A before assemble");
-  if (prec == ORAS_C64 && c->stencil_prec != ORAS_C64)
-    return fail(c, ORAS_E_STATE, "no complex64 stencil assembled");
-  TRY(check_device(c));
+  TRY(oras::check_apply_A(c, x_dev, y_dev, nrhs, prec));
   const long long s = pad_s(nrhs);
   TRY(dev_alloc(c, c->Bint, (size_t)(c->n * s) * sizeof(double2)));
   TRY(dev_alloc(c, c->Tmp, (size_t)(c->n * s) * sizeof(double2)));
-  launch_to_internal((const double2*)x_dev, c->Bint.as<double2>(), c->n, nrhs, (int)s, 0, c->stream);
-  TRY(stencil_internal(c, c->Bint.as<double2>(), nullptr, c->Tmp.as<double2>(), (int)s, prec));
-  launch_from_internal(c->Tmp.as<double2>(), (double2*)y_dev, c->n, nrhs, (int)s, 0, c->stream);
-  HIP_TRY(c, hipGetLastError());
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
-  return ORAS_OK;
+  if (prec == ORAS_C64) TRY(dev_alloc(c, c->Tmp64, (size_t)(c->n * s) * sizeof(float2)));
+  return oras::apply_A_staged(c, x_dev, y_dev, nrhs, prec, c->Bint.as<double2>(),
+                              c->Tmp.as<double2>(),
+                              prec == ORAS_C64 ? c->Tmp64.as<float2>() : nullptr);
 }
 
 oras_status oras_apply_M(oras_ctx c, const void* x_dev, void* y_dev, int nrhs) {

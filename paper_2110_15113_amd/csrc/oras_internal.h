@@ -62,6 +62,7 @@ constexpr int RHS_ALIGN = 8;    // internal right-hand-side count granularity
 // Column count of the plane right-hand-side buffer (blocks of 16 columns).
 __host__ __device__ constexpr inline long long pad16(long long s) { return (s + 15) / 16 * 16; }
 
+
 // Neighbour offset (ex, ey, ez) in {-1,0,1}^3 -> coefficient slot.
 __host__ __device__ constexpr inline int eidx(int ex, int ey, int ez) {
   return (ez + 1) * 9 + (ey + 1) * 3 + (ex + 1);
@@ -111,8 +112,11 @@ void launch_fields(const double* vel, const double* q, const double* m_override,
                    int keep_weights);
 void launch_pml(double2* prof, int n, int npml, double h, double omega, double c_ref, double R0,
                 int power, int low, int high, hipStream_t s);
-// out[0] = max(x); out must hold 1 + 1024 doubles (partial maxima after the first)
-void launch_max_reduce(const double* x, long long n, double* out, hipStream_t s);
+// Validity check of a model array x (n doubles, every entry must be finite and
+// > 0): out[0] = maximum of the valid entries, out[1] = number of invalid
+// ones.  out holds field_check_doubles() doubles (partials after the first two).
+long long field_check_doubles();
+void launch_field_check(const double* x, long long n, double* out, hipStream_t s);
 
 // Stencil: y = A x (or y = b - A x when b != null).  x precision Tx, coefficient
 // precision Tc (== Tx), output double2.
@@ -252,5 +256,13 @@ void launch_weight_gradient(const OpView& op, const double2* qfac, const double*
                             int tab_count, double g0, double dg, const double2* u,
                             const double2* mu, int nrhs, double* scratch, double* g,
                             hipStream_t st);
+
+// ------------------------------------------------- shared by entry points --
+// (defined in oras_api.cpp, which owns the context layout)
+oras_status check_apply_A(oras_ctx c, const void* x_dev, const void* y_dev, int nrhs, int prec);
+// y = A x with x and y staged in the internal layout (xin, yout: n pad8(nrhs)
+// complex128) and, for prec ORAS_C64, x rounded to complex64 in x32
+oras_status apply_A_staged(oras_ctx c, const void* x_dev, void* y_dev, int nrhs, int prec,
+                           double2* xin, double2* yout, float2* x32);
 
 }  // namespace oras

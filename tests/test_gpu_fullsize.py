@@ -4,10 +4,12 @@ The oracle cannot solve these sizes, so it checks sampled outputs and
 properties that hold at any size:
   * the 27 coefficients of sampled rows (windows in the PML, the interior and
     a corner) against the oracle's assembly;
-  * the true residual of the GPU solution meets tol, and the GPU residual
-    b - A x equals the oracle's residual on the sampled windows;
+  * the true residual of the GPU solution meets tol, and so does the oracle's
+    own whole-grid residual b - A x (its coefficients of every row) for two
+    columns, which equals the GPU residual entry by entry;
   * the local solve of one interior subdomain: the ORAS apply at that
-    subdomain's owned nodes equals the oracle's direct solve with its B_j;
+    subdomain's owned nodes equals the oracle's direct solve with its B_j,
+    entry by entry (relative to the box's largest entry);
   * mixed precision: the solution at tol 1e-6 is within 1e-4 (relative L2) of
     the FP64 GPU solution at tol 1e-10 (whose residual is certified above);
   * BLR plane inverses (config 5, eps 1e-3, the benchmark's BLR step): the
@@ -24,7 +26,7 @@ import torch
 from oracle import blr as oblr, direct, operator as op, oras as ooras
 from paper_2110_15113_amd import workloads as wl
 
-from gpu_util import need_gpu, say
+from gpu_util import FP32_BOX, FP64_BOX, need_gpu, say
 
 pytestmark = pytest.mark.gpu
 
@@ -55,29 +57,23 @@ def _check_coefficients(S, F, w):
     del C
 
 
-def _check_residual(S, F, w, b, x, tol):
+def _check_residual(S, F, w, b, x, tol, C):
+    """The GPU's true residual of every column meets tol; for two columns the
+    oracle's own whole-grid residual b - A x (its 27 coefficients C of every
+    row, applied in FP64 on the host) meets tol too and equals the GPU's
+    residual entry by entry."""
     r = b - S.apply_A(x)
     rn = torch.linalg.vector_norm(r.reshape(r.shape[0], -1), dim=1)
     bn = torch.linalg.vector_norm(b.reshape(b.shape[0], -1), dim=1)
     assert bool((rn <= tol * bn * 1.0001).all()), (rn / bn).max().item()
-    for lo in _windows(w):
-        hi = tuple(min(l + 5, n) for l, n in zip(lo, (w.nx, w.ny, w.nz)))
-        C = op.row_coeffs(F, lo, hi)
-        # x on the window grown by one node (zero outside the grid)
-        glo = [max(l - 1, 0) for l in lo]
-        ghi = [min(h + 1, n) for h, n in zip(hi, (w.nx, w.ny, w.nz))]
-        xw = x[:2, glo[2]:ghi[2], glo[1]:ghi[1], glo[0]:ghi[0]].cpu().numpy()
-        pad = np.zeros((2, hi[2] - lo[2] + 2, hi[1] - lo[1] + 2, hi[0] - lo[0] + 2), complex)
-        o = [glo[a] - (lo[a] - 1) for a in range(3)]
-        pad[:, o[2]:o[2] + xw.shape[1], o[1]:o[1] + xw.shape[2], o[0]:o[0] + xw.shape[3]] = xw
-        Ax = np.zeros((2, hi[2] - lo[2], hi[1] - lo[1], hi[0] - lo[0]), complex)
-        for ei, (ex, ey, ez) in enumerate(op.OFFSETS):
-            Ax += C[ei] * pad[:, 1 + ez:pad.shape[1] - 1 + ez, 1 + ey:pad.shape[2] - 1 + ey,
-                              1 + ex:pad.shape[3] - 1 + ex]
-        rw = b[:2, lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]].cpu().numpy() - Ax
-        rg = r[:2, lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]].cpu().numpy()
-        scale = float(bn[:2].max()) + 1e-300
-        assert np.abs(rw - rg).max() <= 1e-11 * scale, lo
+    b2 = b[:2].cpu().numpy()
+    ro = b2 - op.apply_coeffs(C, x[:2].cpu().numpy())
+    ron = np.linalg.norm(ro.reshape(2, -1), axis=1)
+    b2n = np.linalg.norm(b2.reshape(2, -1), axis=1)
+    say(f"  oracle whole-grid residual {(ron / b2n).max():.2e} (tol {tol:.0e})")
+    assert (ron <= tol * b2n * 1.0001).all(), ron / b2n
+    d = np.abs(ro - r[:2].cpu().numpy()).max()
+    assert d <= 1e-11 * b2n.max(), d
 
 
 def _check_local_solve(S, F, w, tol_rel, blr_eps=None):
@@ -108,7 +104,10 @@ def _check_local_solve(S, F, w, tol_rel, blr_eps=None):
 
     ye = local(direct.BlockTridiagLU(B, bs[0] * bs[1], bs[2]))
     if blr_eps is None:
-        err = rel_(z[dst], ye)
+        # element-wise over the owned box, relative to its largest entry per column
+        d = np.abs(z[dst] - ye).reshape(2, -1).max(axis=1)
+        err = float((d / np.abs(ye).reshape(2, -1).max(axis=1)).max())
+        say(f"  local solve of subdomain {s.lo}-{s.hi}: per-box error {err:.2e}")
         assert err <= tol_rel, err
         return
     yb = local(oblr.PlaneSolver(B, bs[0], bs[1], bs[2], blr_eps))
@@ -129,11 +128,16 @@ def test_fp64_workload(cfg):
     F = op.make_fields(w.vel, w.Q, w.omega, w.h, w.npml)
     S = _solver(w, oras.C128)
     _check_coefficients(S, F, w)
-    _check_local_solve(S, F, w, 1e-9)
+    _check_local_solve(S, F, w, FP64_BOX)
     b = S.point_sources(w.sources)
     r = S.solve(b, w.tol, restart=w.restart, maxit=w.maxit)
     assert r.converged.all() and r.rel_res.max() <= w.tol
-    _check_residual(S, F, w, b, r.x, w.tol)
+    C = op.row_coeffs(F)
+    _check_residual(S, F, w, b, r.x, w.tol, C)
+    r = S.solve(b, 1e-10, restart=w.restart, maxit=2000)
+    assert r.converged.all()
+    _check_residual(S, F, w, b, r.x, 1e-10, C)
+    del C
     S.close()
     gc.collect()
     torch.cuda.empty_cache()
@@ -147,11 +151,12 @@ def test_mixed_workload_against_fp64(cfg):
     say(f"full-size mixed config {cfg}")
     F = op.make_fields(w.vel, w.Q, w.omega, w.h, w.npml)
     S = _solver(w, oras.C64)
-    _check_local_solve(S, F, w, 1e-3)
+    _check_local_solve(S, F, w, FP32_BOX)
     b = S.point_sources(w.sources)
     rm = S.solve(b, w.tol, restart=w.restart, maxit=w.maxit)
     assert rm.converged.all() and rm.rel_res.max() <= w.tol
-    _check_residual(S, F, w, b, rm.x, w.tol)
+    C = op.row_coeffs(F)
+    _check_residual(S, F, w, b, rm.x, w.tol, C)
     xm = rm.x.clone()
     xb = None
     if cfg == 5:
@@ -160,7 +165,7 @@ def test_mixed_workload_against_fp64(cfg):
         _check_local_solve(S, F, w, 1e-3, blr_eps=1e-3)
         rb = S.solve(b, w.tol, restart=w.restart, maxit=w.maxit)
         assert rb.converged.all() and rb.rel_res.max() <= w.tol
-        _check_residual(S, F, w, b, rb.x, w.tol)
+        _check_residual(S, F, w, b, rb.x, w.tol, C)
         xb = rb.x.clone()
         del rb
     S.close()
@@ -172,7 +177,8 @@ def test_mixed_workload_against_fp64(cfg):
     b = S.point_sources(w.sources)
     rt = S.solve(b, 1e-10, restart=w.restart, maxit=2000)
     assert rt.converged.all()
-    _check_residual(S, F, w, b, rt.x, 1e-10)
+    _check_residual(S, F, w, b, rt.x, 1e-10, C)
+    del C
     err = (torch.linalg.vector_norm((xm - rt.x).reshape(-1))
            / torch.linalg.vector_norm(rt.x.reshape(-1))).item()
     say(f"config {cfg}: mixed(1e-6) vs fp64(1e-10) relative L2 = {err:.3e}")
@@ -182,6 +188,95 @@ def test_mixed_workload_against_fp64(cfg):
                 / torch.linalg.vector_norm(rt.x.reshape(-1))).item()
         say(f"config {cfg}: mixed BLR(1e-6) vs fp64(1e-10) relative L2 = {errb:.3e}")
         assert errb <= 1e-4, errb
+    S.close()
+    gc.collect()
+    torch.cuda.empty_cache()
+
+
+def test_config4_gradient_at_size():
+    """The differentiation workload at its size (96^3, 32 sources, 400
+    receivers, complex128, solves to 1e-12): the autograd gradient of the
+    receiver misfit at the start model against central differences along 20
+    seeded directions (step 1e-4 of max m), and the GPU gradient against the
+    oracle's adjoint gradient evaluated on the GPU's u and mu; the gradient of
+    the map whose weights follow m (sec. 2.3) against the oracle's exact
+    gradient, likewise."""
+    need_gpu()
+    from paper_2110_15113_amd import oras
+    from paper_2110_15113_amd.autograd import ForwardSetup, receiver_data
+    from oracle import adjoint
+    w = wl.CONFIGS[4]()
+    say("config 4 gradient at size")
+    tol = 1e-12
+    S = oras.Solver(0)
+    dev = S.device
+    S.assemble(torch.as_tensor(w.vel_start, device=dev), w.h, w.npml, w.omega, None,
+               prec=oras.C128)                   # weights frozen at the start model
+    fs = ForwardSetup(S, w.sources, w.receivers, w.parts, w.overlap, oras.C128, tol,
+                      restart=w.restart)
+    m_true = torch.as_tensor(1.0 / w.vel ** 2, device=dev)
+    m0 = torch.as_tensor(1.0 / w.vel_start ** 2, device=dev)
+    with torch.no_grad():
+        d_obs = receiver_data(m_true, fs).clone()
+
+    def J(m):
+        return 0.5 * (receiver_data(m, fs) - d_obs).abs().pow(2).sum()
+
+    m = m0.clone().requires_grad_(True)
+    J(m).backward()
+    g = m.grad.clone()
+    # central differences along 20 seeded Gaussian directions over the
+    # physical cells, unit max-norm, step 1e-4 of max m
+    rng = np.random.default_rng(40)
+    phys = np.zeros(w.vel.shape)
+    p = w.npml
+    phys[p:-p, p:-p, p:-p] = 1.0
+    step = 1e-4 * float(m0.max())
+    worst = 0.0
+    for t in range(20):
+        d = rng.standard_normal(w.vel.shape) * phys
+        d = torch.as_tensor(d / np.abs(d).max(), device=dev)
+        with torch.no_grad():
+            fd = float((J(m0 + step * d) - J(m0 - step * d)) / (2 * step))
+        an = float((g * d).sum())
+        worst = max(worst, abs(fd - an) / abs(an))
+        assert abs(fd - an) <= 1e-4 * abs(an), (t, fd, an)
+    say(f"  20 directions: worst relative gap autograd vs differences {worst:.2e}")
+
+    def fields(weights):
+        """u and mu at the current model of S, as the backward pass forms them."""
+        b = S.point_sources(w.sources)
+        u = S.solve(b, tol, restart=w.restart, maxit=2000)
+        assert u.converged.all()
+        res = S.sample(u.x, w.receivers) - d_obs
+        mu = S.solve(S.spread(res, w.receivers), tol, restart=w.restart, maxit=2000, conj=True)
+        assert mu.converged.all()
+        return u.x, mu.x, S.gradient(u.x, mu.x, weights=weights)
+
+    # frozen weights at m0: the gradient the map differentiates
+    S.set_m(m0)
+    S.factor(w.parts, w.overlap, oras.C128)
+    u, mu, gg = fields(False)
+    assert float((gg - g).abs().max()) <= 1e-9 * float(g.abs().max())
+    F0 = op.make_fields(w.vel_start, None, w.omega, w.h, w.npml)
+    U, MU = u.cpu().numpy(), mu.cpu().numpy()
+    ref = adjoint.gradient(F0, U, MU)
+    e = np.abs(gg.cpu().numpy() - ref).max() / np.abs(ref).max()
+    say(f"  gradient vs oracle on the GPU's u and mu: {e:.2e}")
+    assert e <= 1e-10, e
+    # weights that follow m, at the true model with a 1 % smooth perturbation
+    # (a homogeneous region puts G on a knot of the weight table, where the
+    # table slope is one-sided and either side is a valid reading)
+    pert = 1.0 + 0.01 * (2.0 * wl.smooth_field(w.vel.shape, w.h, 100.0, rng) - 1.0)
+    m1_np = (1.0 / w.vel ** 2) * pert
+    S.set_m(torch.as_tensor(m1_np, device=dev), weights="follow")
+    S.factor(w.parts, w.overlap, oras.C128)
+    u, mu, gx = fields(True)
+    F1 = adjoint.fields_from_m(m1_np, None, w.omega, w.h, w.npml, float(w.vel_start.max()))
+    ref = adjoint.gradient_exact(F1, u.cpu().numpy(), mu.cpu().numpy(), m1_np)
+    e = np.abs(gx.cpu().numpy() - ref).max() / np.abs(ref).max()
+    say(f"  exact gradient vs oracle on the GPU's u and mu: {e:.2e}")
+    assert e <= 1e-10, e
     S.close()
     gc.collect()
     torch.cuda.empty_cache()
