@@ -470,7 +470,8 @@ def main():
         bytes_per = gb / gl
         peak = PEAK["fp32_mfma_TFLOPs"] if P == oras.C64 else PEAK["fp64_mfma_TFLOPs"]
         ach = flops_per / avg / 1e12
-        kname = ("plane_gemm_f32_kernel (MFMA 32x32x2 f32, local substitutions)" if P == oras.C64
+        kname = ("plane_gemm_x3_kernel (complex FP32 products on MFMA 32x32x16 bf16 with exact "
+                 "three-piece operand splits, local substitutions)" if P == oras.C64
                  else "plane_gemm_f64_kernel (MFMA 16x16x4 f64, local substitutions)")
         if args.blr is not None:
             kname = ("blr_gemm_f32_kernel projection + expansion (MFMA 32x32x2 f32, BLR local "
@@ -485,14 +486,17 @@ def main():
                 "algorithmic_bytes_per_launch": bytes_per, "algorithmic_flops_per_launch": flops_per,
                 "avg_launch_us": avg * 1e6, "launches": gl,
                 "achieved_GBps": round(bytes_per / avg / 1e9, 1)}
-        if args.blr is not None:
-            # the compressed blocks carry 8 s flops per stored entry but every
-            # plane step also moves the gathered and written rows: 14-15 flop/B,
-            # below the FP32 ridge (19.7), so the pair is bounded by HBM
+        if P == oras.C64:
+            # The FP32-accurate products run on the bf16 instruction (six piece
+            # products per real product), whose dense peak is 16 times the FP32
+            # one: 8 p^2 s flops at that rate need a fraction of the time the
+            # p^2 factor entries take to stream from HBM, so the kernel is
+            # bounded by HBM (also in BLR form: 14-15 flop/B below the ridge).
             gbps = bytes_per / avg / 1e9
             roof.update({"bound": "hbm", "achieved": round(gbps, 1), "peak": PEAK["hbm_GBps"],
                          "unit": "GB/s", "frac": round(gbps / PEAK["hbm_GBps"], 4),
-                         "achieved_TFLOPs": round(ach, 2)})
+                         "achieved_TFLOPs": round(ach, 2),
+                         "fp32_equivalent_frac_of_fp32_mfma_peak": round(ach / peak, 4)})
     rel_res = float(np.max(last.rel_res[:nrhs]))
     out = {
         "metric": "RHS solved/s to 1e-6 residual, mixed vs FP64 ORAS-FGMRES; 27-pt apply GB/s",

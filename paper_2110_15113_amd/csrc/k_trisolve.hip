@@ -18,19 +18,15 @@
 // Boolean partition of unity: each output entry is written once, no
 // atomics).
 //
-// Complex products on real MFMA: with A = Ar + i Ai and B = Br + i Bi, the
-// interleaved output columns (Re, Im) of C = A B come from two real products
-// per k-slice, Ar * [Br | Bi] + Ai * [-Bi | Br].
+// Complex FP32 (the mixed-precision path) runs its products on the bf16
+// matrix instruction with every FP32 operand split exactly into three bf16
+// pieces (see the section below): the real and imaginary parts of the result
+// accumulate separately, Re = Ar Br - Ai Bi and Im = Ar Bi + Ai Br, six piece
+// products each, and the kernel streams S_k^{-1} at HBM speed.
 //
-// Complex FP32 (the mixed-precision path) uses the 32x32x2 instruction, which
-// on gfx950 sustains its full rate from a single wave with four independent
-// accumulators (the 16x16x4 form does not).  t is written by the
-// right-hand-side kernel directly in the operand order of that instruction,
-// so each wave fetches one 1 KB row of A and one 1 KB block of t per 4-deep
-// k-slice pair with no lane duplication; the second real operand [-Bi | Br]
-// is formed by swapping adjacent lanes (DPP).
-//
-// Complex FP64 uses the 16x16x4 FP64 instruction with t in row-major order.
+// Complex FP64 uses the 16x16x4 FP64 instruction with t in row-major order;
+// the interleaved output columns (Re, Im) of C = A B come from two real
+// products per k-slice, Ar * [Br | Bi] + Ai * [-Bi | Br].
 //
 // Work-groups are one wave.  The hardware hands consecutive work-group ids to
 // the 8 XCDs in turn, so the linear id is mapped such that all waves of one
@@ -111,40 +107,91 @@ __device__ inline C<R> plane_rhs_entry(const SubDesc& sd, int k, int bwd, int q,
   return t;
 }
 
-// ------------------------------------------------------- complex FP32 path --
-// t in operand order: per subdomain, per block cb of 16 columns, per group g
-// of 8 plane rows, per lane (h = lane / 32, rr = lane % 32) one float4 whose
-// component 2 p + e is part (rr & 1) of t[8 g + 4 p + 2 h + e][16 cb + rr / 2]
-// (zero beyond the plane or beyond column s).
-//
-// A work-group forms t for 32 plane rows (four groups of 8) and 32 columns
-// (two column blocks).  Eight lanes share a row, four columns each, so every
-// vector load of y or v covers whole cache lines of one row and a coupling
-// coefficient is one broadcast per row, loaded once per four columns (with
-// sixteen lanes of two columns: 63.2 against 61.9 us per plane step on 160^3,
-// 32 RHS); the tile is transposed through LDS and written out as whole float4
-// operands, two per thread.
+// The right-hand-side kernel of the complex FP32 path forms t for 32 plane
+// rows and 32 columns per work-group: eight lanes share a row, four columns
+// each, so every vector load of y or v covers whole cache lines of one row
+// and a coupling coefficient is one broadcast per row, loaded once per four
+// columns (with sixteen lanes of two columns: 63.2 against 61.9 us per plane
+// step on 160^3, 32 RHS).
 constexpr int RB_ROWS = 32;
 constexpr int RB_THREADS = RB_ROWS * 8;
 
+// The factor rows are streamed once per launch: non-temporal loads keep them
+// from evicting the t operand, which every row tile of a subdomain re-reads
+// from L2 (400 -> 394 us per plane step on 160^3, 32 RHS, with the FP32
+// instruction).
+typedef float f32x4nt __attribute__((ext_vector_type(4)));
+__device__ inline float4 ld_nt(const float4* p) {
+  const f32x4nt v = __builtin_nontemporal_load(reinterpret_cast<const f32x4nt*>(p));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+
+// ------------------------------------- complex FP32 on bf16 matrix cores --
+// The FP32 products run on the bf16 MFMA (32x32x16), which has 16 times the
+// dense FP32 MFMA rate on gfx950.  Every FP32 operand is split exactly into
+// three bf16 pieces, x = x1 + x2 + x3 (each piece the round-to-nearest of what
+// the previous ones leave; an FP32 significand of 24 bits leaves at most 8
+// bits for the last piece, so the split loses nothing), and a real product
+// a b is formed from the six piece products whose size is at least 2^-16 of
+// a1 b1: a1 b1, a1 b2, a2 b1, a1 b3, a3 b1, a2 b2.  The three products left
+// out are below 2^-24 |a b|, so each product carries an FP32-level error and
+// the MFMA accumulates in FP32, as the FP32 instruction does.  The kernel then
+// streams S_k^{-1} at HBM speed instead of waiting on the FP32 MFMA rate.
+//
+// t is kept already split by the right-hand-side kernel (it is re-read by
+// every row tile of a subdomain), per subdomain, per chunk cc of 32 columns,
+// per half tile hj of 16 plane rows, per piece pi (0..2: real part, 3..5:
+// imaginary part), per lane (n = lane % 32 the column, g = lane / 32): one
+// 16-byte group of eight bf16 values, value i being the piece of
+// t[16 hj + 4 (i / 2) + 2 g + i % 2][32 cc + n].  That row order matches the
+// factor rows a lane loads from the tile layout (lane (r, g): row r, entries
+// 4 q + 2 g + e of the half tile for q = 0..3, e = 0..1), so value i of the A
+// and B operands of the instruction refer to the same k.
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+// Two FP32 values rounded to bf16 (round to nearest even), packed: a low, b high.
+__device__ inline unsigned pack_bf16(float a, float b) {
+  const f32x2 v = {a, b};
+  return __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2));
+}
+__device__ inline float bf16_lo(unsigned p) { return __builtin_bit_cast(float, p << 16); }
+__device__ inline float bf16_hi(unsigned p) { return __builtin_bit_cast(float, p & 0xffff0000u); }
+// a = a1 + a2 + a3 and b likewise, each piece word holding (a_i, b_i).
+__device__ inline void split3(float a, float b, unsigned& w1, unsigned& w2, unsigned& w3) {
+  w1 = pack_bf16(a, b);
+  a -= bf16_lo(w1);
+  b -= bf16_hi(w1);
+  w2 = pack_bf16(a, b);
+  a -= bf16_lo(w2);
+  b -= bf16_hi(w2);
+  w3 = pack_bf16(a, b);
+}
+__device__ inline bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+// Right-hand side of 32 plane rows and one 32-column chunk, written as pieces.
+// Eight lanes share a plane row, four columns each (one coupling load per four
+// columns); the tile then goes through LDS and each thread writes the three
+// pieces of one part of one lane's values.
 __global__ void __launch_bounds__(RB_THREADS)
-plane_rhs_f32_kernel(const SubDesc* __restrict__ subs, int nsub, int nrb, int ncc, int k, int bwd,
-                     const float2* __restrict__ lca, const float2* __restrict__ ybuf,
-                     float4* __restrict__ tvm, const double2* __restrict__ v,
-                     const double* __restrict__ scale, int nx, int ny, int s, int s16) {
+plane_rhs_x3_kernel(const SubDesc* __restrict__ subs, int nsub, int nrb, int ncc, int k, int bwd,
+                    const float2* __restrict__ lca, const float2* __restrict__ ybuf,
+                    u32x4* __restrict__ tp, const double2* __restrict__ v,
+                    const double* __restrict__ scale, int nx, int ny, int s, int s32) {
   __shared__ float2 tile[RB_ROWS][33];
   int sub, item;
   xcd_map(nrb * ncc, sub, item);
   if (sub >= nsub) return;
   const SubDesc sd = subs[sub];
   if (!plane_active(sd, k, bwd)) return;
-  const int G = sd.P / 8;
-  const int cc = item / nrb, g0 = 4 * (item % nrb);
-  if (g0 >= G) return;
+  const int cc = item / nrb, q0 = RB_ROWS * (item % nrb);
+  if (q0 >= sd.P) return;
 
   const int tid = threadIdx.x;
   const int rl = tid >> 3, cp = tid & 7;
-  const int q = 8 * g0 + rl;
+  const int q = q0 + rl;
   const int c = 32 * cc + 4 * cp;
   float2 t[4];
 #pragma unroll
@@ -189,183 +236,149 @@ plane_rhs_f32_kernel(const SubDesc* __restrict__ subs, int nsub, int nrb, int nc
 #pragma unroll
   for (int j = 0; j < 4; ++j) tile[rl][4 * cp + j] = t[j];
   __syncthreads();
-  // two float4 per thread: column block 2 cc + cbl, row group g0 + gl, lane
+  // thread -> (half tile hl of the two, part, lane (n, g)); 8 values each
+  const int hl = tid >> 7, part = (tid >> 6) & 1, lane = tid & 63;
+  const int n = lane & 31, g = lane >> 5;
+  float val[8];
 #pragma unroll
-  for (int o = 0; o < 2; ++o) {
-    const int idx = tid + RB_THREADS * o;
-    const int cbl = idx >> 8, gl = (idx >> 6) & 3, lane = idx & 63;
-    const int cb = 2 * cc + cbl;
-    if (cb >= s16 / 16 || g0 + gl >= G) continue;
-    const int h = lane >> 5, rr = lane & 31, ci = 16 * cbl + (rr >> 1);
-    float val[4];
-#pragma unroll
-    for (int j4 = 0; j4 < 4; ++j4) {
-      const float2 w = tile[8 * gl + 4 * (j4 >> 1) + 2 * h + (j4 & 1)][ci];
-      val[j4] = (rr & 1) ? w.y : w.x;
-    }
-    tvm[sd.tv_off * s16 / 2 + ((long long)cb * G + g0 + gl) * 64 + lane] =
-        make_float4(val[0], val[1], val[2], val[3]);
+  for (int i = 0; i < 8; ++i) {
+    const float2 w = tile[16 * hl + 4 * (i >> 1) + 2 * g + (i & 1)][n];
+    val[i] = part ? w.y : w.x;
   }
+  unsigned p1[4], p2[4], p3[4];
+#pragma unroll
+  for (int d = 0; d < 4; ++d) split3(val[2 * d], val[2 * d + 1], p1[d], p2[d], p3[d]);
+  const int hj = q0 / 16 + hl;
+  u32x4* out = tp + sd.tv_off * s32 * 3 / 4 +
+               (((long long)cc * (sd.P / 16) + hj) * 6 + 3 * part) * 64 + lane;
+  out[0] = u32x4{p1[0], p1[1], p1[2], p1[3]};
+  out[64] = u32x4{p2[0], p2[1], p2[2], p2[3]};
+  out[128] = u32x4{p3[0], p3[1], p3[2], p3[3]};
 }
 
-// Y_k (=|-=) S_k^{-1} t for one 32-row tile and NB blocks of 16 columns (one
-// wave).  A row of the factor tile layout holds, for each 4-k slice, rows
-// r = lane % 32 with entries 2 h, 2 h + 1 (h = lane / 32) in one float4; the
-// matching t operands come from the float4 of the operand-order layout.  The
-// operands advance by half tiles of 16 k: the next half tile of both is
-// prefetched into registers while the current one feeds 8 NB instructions.
-// The half-tile buffers keep the wave within 168 registers, so three waves
-// share a SIMD (whole 32-k tiles took 202 registers and allowed two).
-// The factor rows are streamed once per launch: non-temporal loads keep them
-// from evicting the t operand, which every row tile of a subdomain re-reads
-// from L2 (400 -> 394 us per plane step on 160^3, 32 RHS).
-typedef float f32x4nt __attribute__((ext_vector_type(4)));
-__device__ inline float4 ld_nt(const float4* p) {
-  const f32x4nt v = __builtin_nontemporal_load(reinterpret_cast<const f32x4nt*>(p));
-  return make_float4(v.x, v.y, v.z, v.w);
-}
-
-template <typename Z, int NB>
+// Y_k (=|-=) S_k^{-1} t for one 32-row tile and one 32-column chunk (one
+// wave), on the bf16 instruction with split operands.  The real and imaginary
+// parts of the result are separate accumulators:
+//   Re += Ar Br - Ai Bi,  Im += Ar Bi + Ai Br,
+// six piece products each, 24 instructions per 16 k.  The next half tile of
+// the factor rows and of the t pieces is fetched while the current one feeds
+// the products; the factor rows are streamed once (non-temporal loads).
+template <typename Z>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3)))
-plane_gemm_f32_kernel(const SubDesc* __restrict__ subs, int nsub, int max_nt, int ncg, int cb0,
-                      int k, int bwd, const float2* __restrict__ fac,
-                      const float4* __restrict__ tvm, float2* __restrict__ ybuf,
-                      Z* __restrict__ z, int nx, int ny, int s, int s16) {
+plane_gemm_x3_kernel(const SubDesc* __restrict__ subs, int nsub, int max_nt, int ncc, int k,
+                     int bwd, const float2* __restrict__ fac, const u32x4* __restrict__ tp,
+                     float2* __restrict__ ybuf, Z* __restrict__ z, int nx, int ny, int s,
+                     int s32) {
   using ZR = typename Comp<Z>::type;
   int sub, item;
-  xcd_map(max_nt * ncg, sub, item);
+  xcd_map(max_nt * ncc, sub, item);
   if (sub >= nsub) return;
   const SubDesc sd = subs[sub];
   if (!plane_active(sd, k, bwd)) return;
-  const int I = item / ncg, cg = item % ncg;
+  const int I = item / ncc, cc = item % ncc;
   const int nt = sd.nt;
   if (I >= nt) return;
-  const int P = sd.P, G = P / 8;
-  const int cbf = cb0 + cg * NB;   // first column block of this wave
+  const int P = sd.P;
   const float4* A4 = reinterpret_cast<const float4*>(fac + sd.fac_off + (long long)k * P * P) +
                      (long long)I * nt * 512;
-  const float4* B4 = tvm + sd.tv_off * s16 / 2 + (long long)cbf * G * 64;
-  const int lane = threadIdx.x, rr = lane & 31, h = lane >> 5;
-  const int aoff = rr * 2 + h;
-  const bool odd = (rr & 1) != 0;
+  const u32x4* B = tp + sd.tv_off * s32 * 3 / 4 + (long long)cc * (P / 16) * 6 * 64;
+  const int lane = threadIdx.x, rr = lane & 31, g = lane >> 5;
+  const int aoff = rr * 2 + g;
 
-  f32x16 acc[NB][2];
+  f32x16 accR, accI;
 #pragma unroll
-  for (int b = 0; b < NB; ++b)
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      acc[b][0][j] = 0.f;
-      acc[b][1][j] = 0.f;
-    }
-  // half tiles of 16 k: 4 float4 of A and 2 x NB float4 of t per lane
-  float4 sa[4], sb[2][NB];
+  for (int j = 0; j < 16; ++j) {
+    accR[j] = 0.f;
+    accI[j] = 0.f;
+  }
+  float4 sa[4];
+  u32x4 sb[6];
 #pragma unroll
   for (int q = 0; q < 4; ++q) sa[q] = ld_nt(&A4[q * 64 + aoff]);
 #pragma unroll
-  for (int gg = 0; gg < 2; ++gg)
-#pragma unroll
-    for (int b = 0; b < NB; ++b) sb[gg][b] = B4[((long long)b * G + gg) * 64 + lane];
+  for (int pi = 0; pi < 6; ++pi) sb[pi] = B[pi * 64 + lane];
 
   for (int HJ = 0; HJ < 2 * nt; ++HJ) {
-    float4 ca[4], cbv[2][NB];
+    float4 ca[4];
+    u32x4 cb[6];
 #pragma unroll
     for (int q = 0; q < 4; ++q) ca[q] = sa[q];
 #pragma unroll
-    for (int gg = 0; gg < 2; ++gg)
-#pragma unroll
-      for (int b = 0; b < NB; ++b) cbv[gg][b] = sb[gg][b];
+    for (int pi = 0; pi < 6; ++pi) cb[pi] = sb[pi];
     if (HJ + 1 < 2 * nt) {
       const int J1 = (HJ + 1) >> 1, h1 = (HJ + 1) & 1;
 #pragma unroll
       for (int q = 0; q < 4; ++q) sa[q] = ld_nt(&A4[(long long)J1 * 512 + (4 * h1 + q) * 64 + aoff]);
 #pragma unroll
-      for (int gg = 0; gg < 2; ++gg)
-#pragma unroll
-        for (int b = 0; b < NB; ++b)
-          sb[gg][b] = B4[((long long)b * G + 4 * J1 + 2 * h1 + gg) * 64 + lane];
+      for (int pi = 0; pi < 6; ++pi) sb[pi] = B[((long long)(HJ + 1) * 6 + pi) * 64 + lane];
     }
+    // value i = 2 q + e of the lane: real / imaginary part of entry e of ca[q]
+    unsigned r1[4], r2[4], r3[4], i1[4], i2[4], i3[4];
 #pragma unroll
-    for (int gg = 0; gg < 2; ++gg)
-#pragma unroll
-      for (int p = 0; p < 2; ++p) {
-        const float4 a = ca[2 * gg + p];
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-          const float ar = e ? a.z : a.x, ai = e ? a.w : a.y;
-#pragma unroll
-          for (int b = 0; b < NB; ++b) {
-            const float4 bv = cbv[gg][b];
-            const float b1 = p ? (e ? bv.w : bv.z) : (e ? bv.y : bv.x);
-            const float sw = __int_as_float(__builtin_amdgcn_update_dpp(
-                __float_as_int(b1), __float_as_int(b1), 0xB1, 0xF, 0xF, false));
-            const float b2 = odd ? sw : -sw;
-            acc[b][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, b1, acc[b][0], 0, 0, 0);
-            acc[b][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, b2, acc[b][1], 0, 0, 0);
-          }
-        }
-      }
+    for (int q = 0; q < 4; ++q) {
+      split3(ca[q].x, ca[q].z, r1[q], r2[q], r3[q]);
+      split3(ca[q].y, ca[q].w, i1[q], i2[q], i3[q]);
+    }
+    const bf16x8 Ar1 = as_bf16x8(u32x4{r1[0], r1[1], r1[2], r1[3]});
+    const bf16x8 Ar2 = as_bf16x8(u32x4{r2[0], r2[1], r2[2], r2[3]});
+    const bf16x8 Ar3 = as_bf16x8(u32x4{r3[0], r3[1], r3[2], r3[3]});
+    const bf16x8 Ai1 = as_bf16x8(u32x4{i1[0], i1[1], i1[2], i1[3]});
+    const bf16x8 Ai2 = as_bf16x8(u32x4{i2[0], i2[1], i2[2], i2[3]});
+    const bf16x8 Ai3 = as_bf16x8(u32x4{i3[0], i3[1], i3[2], i3[3]});
+    const u32x4 sgn = {0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+    const bf16x8 Ni1 = as_bf16x8(u32x4{i1[0], i1[1], i1[2], i1[3]} ^ sgn);
+    const bf16x8 Ni2 = as_bf16x8(u32x4{i2[0], i2[1], i2[2], i2[3]} ^ sgn);
+    const bf16x8 Ni3 = as_bf16x8(u32x4{i3[0], i3[1], i3[2], i3[3]} ^ sgn);
+    const bf16x8 Br1 = as_bf16x8(cb[0]), Br2 = as_bf16x8(cb[1]), Br3 = as_bf16x8(cb[2]);
+    const bf16x8 Bi1 = as_bf16x8(cb[3]), Bi2 = as_bf16x8(cb[4]), Bi3 = as_bf16x8(cb[5]);
+#define ORAS_X3(AR, AI, NI, BR, BI)                                              \
+  accR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(AR, BR, accR, 0, 0, 0);         \
+  accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(AR, BI, accI, 0, 0, 0);         \
+  accR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(NI, BI, accR, 0, 0, 0);         \
+  accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(AI, BR, accI, 0, 0, 0);
+    ORAS_X3(Ar1, Ai1, Ni1, Br1, Bi1)
+    ORAS_X3(Ar1, Ai1, Ni1, Br2, Bi2)
+    ORAS_X3(Ar2, Ai2, Ni2, Br1, Bi1)
+    ORAS_X3(Ar1, Ai1, Ni1, Br3, Bi3)
+    ORAS_X3(Ar3, Ai3, Ni3, Br1, Bi1)
+    ORAS_X3(Ar2, Ai2, Ni2, Br2, Bi2)
+#undef ORAS_X3
   }
 
-  // accumulator item i of lane l: row 8 (i / 4) + 4 (l / 32) + i % 4, real column l % 32
+  // accumulator item i of lane l: row 8 (i / 4) + 4 (l / 32) + i % 4, column l % 32
   const bool final_plane = bwd || (k == sd.sz - 1);
-  float* Yk = reinterpret_cast<float*>(ybuf + (sd.y_off + (long long)k * P) * s);
+  const int col = 32 * cc + rr;
+  float2* Yk = ybuf + (sd.y_off + (long long)k * P) * s;
+  const int colc = min(col, s - 1);
   // backward: read every old value first (all loads in flight together)
-  float old[16][NB];
+  float2 old[16];
 #pragma unroll
-  for (int i = 0; i < 16; ++i)
-#pragma unroll
-    for (int b = 0; b < NB; ++b) old[i][b] = 0.f;
+  for (int i = 0; i < 16; ++i) old[i] = make_float2(0.f, 0.f);
   if (bwd) {
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-      const int row = I * TILE + 8 * (i / 4) + 4 * h + (i % 4);
-#pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        const int col = min(16 * (cbf + b) + (rr >> 1), s - 1);
-        old[i][b] = Yk[(long long)row * 2 * s + 2 * col + (rr & 1)];
-      }
+      const int row = I * TILE + 8 * (i / 4) + 4 * g + (i % 4);
+      old[i] = Yk[(long long)row * s + colc];
     }
   }
+  if (col >= s) return;
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
-    const int row = I * TILE + 8 * (i / 4) + 4 * h + (i % 4);
-    float* yr = Yk + (long long)row * 2 * s;
-    long long zoff = -1;
+    const int row = I * TILE + 8 * (i / 4) + 4 * g + (i % 4);
+    float2 val = make_float2(accR[i], accI[i]);
+    if (bwd) val = make_float2(old[i].x - val.x, old[i].y - val.y);
+    Yk[(long long)row * s + col] = val;
     if (final_plane && row < sd.p) {
       const int qx = row % sd.sx, qy = row / sd.sx;
       const int gx = sd.lo[0] + qx, gy = sd.lo[1] + qy, gz = sd.lo[2] + k;
       if (gx >= sd.olo[0] && gx < sd.ohi[0] && gy >= sd.olo[1] && gy < sd.ohi[1] &&
-          gz >= sd.olo[2] && gz < sd.ohi[2])
-        zoff = (((long long)gz * ny + gy) * nx + gx) * s;
-    }
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const int col = 16 * (cbf + b) + (rr >> 1);
-      if (col >= s) continue;
-      const int fi = 2 * col + (rr & 1);
-      float val = acc[b][0][i] + acc[b][1][i];
-      if (bwd) val = old[i][b] - val;
-      yr[fi] = val;
-      if (zoff >= 0) reinterpret_cast<ZR*>(z + zoff)[fi] = (ZR)val;
+          gz >= sd.olo[2] && gz < sd.ohi[2]) {
+        ZR* zp = reinterpret_cast<ZR*>(z + (((long long)gz * ny + gy) * nx + gx) * s + col);
+        zp[0] = (ZR)val.x;
+        zp[1] = (ZR)val.y;
+      }
     }
   }
-}
-
-template <typename Z>
-void gemm_f32_dispatch(const OrasPlan& pl, int k, int bwd, const float2* fac, const float4* tvm,
-                       float2* ybuf, Z* z, int nx, int ny, int s, hipStream_t st) {
-  const int s16 = (int)pad16(s);
-  const int nblk = s16 / 16;
-  const int nsub8 = (pl.nsub + NXCD - 1) / NXCD * NXCD;
-  const int pairs = nblk / 2;
-  if (pairs > 0)
-    hipLaunchKernelGGL((plane_gemm_f32_kernel<Z, 2>), dim3((unsigned)(nsub8 * pl.max_nt * pairs)),
-                       dim3(64), 0, st, pl.subs, pl.nsub, pl.max_nt, pairs, 0, k, bwd, fac, tvm,
-                       ybuf, z, nx, ny, s, s16);
-  if (nblk % 2)
-    hipLaunchKernelGGL((plane_gemm_f32_kernel<Z, 1>), dim3((unsigned)(nsub8 * pl.max_nt)), dim3(64),
-                       0, st, pl.subs, pl.nsub, pl.max_nt, 1, nblk - 1, k, bwd, fac, tvm, ybuf, z,
-                       nx, ny, s, s16);
 }
 
 // ------------------------------------------------------- complex FP64 path --
@@ -501,16 +514,18 @@ template <typename Z>
 void plane_step_f32(const OrasPlan& pl, int k, int bwd, const float2* fac, const float2* lca,
                     float2* ybuf, float2* tvbuf, const double2* v, const double* scale, Z* z,
                     int nx, int ny, int s, hipStream_t st, hipEvent_t* ev) {
-  const int s16 = (int)pad16(s);
+  const int s32 = (int)pad32(s);
   const int nrb = (int)((pl.max_p + RB_ROWS - 1) / RB_ROWS);   // 32-row blocks
-  const int ncc = (s16 + 31) / 32;                               // 32-column chunks
+  const int ncc = s32 / 32;                                      // 32-column chunks
   const int nsub8 = (pl.nsub + NXCD - 1) / NXCD * NXCD;
-  hipLaunchKernelGGL(plane_rhs_f32_kernel, dim3((unsigned)(nsub8 * nrb * ncc)), dim3(RB_THREADS), 0,
-                     st, pl.subs, pl.nsub, nrb, ncc, k, bwd, lca, ybuf,
-                     reinterpret_cast<float4*>(tvbuf), v, scale, nx, ny, s, s16);
+  u32x4* tp = reinterpret_cast<u32x4*>(tvbuf);
+  hipLaunchKernelGGL(plane_rhs_x3_kernel, dim3((unsigned)(nsub8 * nrb * ncc)), dim3(RB_THREADS), 0,
+                     st, pl.subs, pl.nsub, nrb, ncc, k, bwd, lca, ybuf, tp, v, scale, nx, ny, s,
+                     s32);
   if (ev) (void)hipEventRecord(ev[0], st);
-  gemm_f32_dispatch<Z>(pl, k, bwd, fac, reinterpret_cast<const float4*>(tvbuf), ybuf, z, nx, ny,
-                       s, st);
+  hipLaunchKernelGGL((plane_gemm_x3_kernel<Z>), dim3((unsigned)(nsub8 * pl.max_nt * ncc)), dim3(64),
+                     0, st, pl.subs, pl.nsub, pl.max_nt, ncc, k, bwd, fac, tp, ybuf, z, nx, ny, s,
+                     s32);
   if (ev) (void)hipEventRecord(ev[1], st);
 }
 

@@ -262,8 +262,7 @@ oras_status stencil_internal(oras_ctx c, const double2* x, const double2* b, dou
 oras_status ensure_oras_ws(oras_ctx c, long long s) {
   const size_t cs = csize(c->factor_prec);
   TRY(dev_alloc(c, c->ybuf, (size_t)(c->y_rows * s) * cs));
-  // the plane right-hand side is laid out in blocks of 16 columns
-  TRY(dev_alloc(c, c->tvbuf, (size_t)(c->tv_rows * pad16(s)) * cs));
+  TRY(dev_alloc(c, c->tvbuf, plane_rhs_bytes(c->factor_prec, c->tv_rows, s)));
   return ORAS_OK;
 }
 

@@ -61,6 +61,15 @@ constexpr int TILE = 32;        // factor tile edge (complex entries)
 constexpr int RHS_ALIGN = 8;    // internal right-hand-side count granularity
 // Column count of the plane right-hand-side buffer (blocks of 16 columns).
 __host__ __device__ constexpr inline long long pad16(long long s) { return (s + 15) / 16 * 16; }
+__host__ __device__ constexpr inline long long pad32(long long s) { return (s + 31) / 32 * 32; }
+// Bytes of the plane right-hand-side buffer for tv_rows plane rows and s
+// columns.  Complex FP32 factors take t as three bf16 pieces of each real and
+// imaginary part (12 bytes per complex entry) in chunks of 32 columns;
+// complex FP64 factors take t row-major in blocks of 16 columns.
+inline size_t plane_rhs_bytes(int factor_prec, long long tv_rows, long long s) {
+  return factor_prec == ORAS_C64 ? (size_t)(tv_rows * pad32(s)) * 12
+                                 : (size_t)(tv_rows * pad16(s)) * sizeof(double2);
+}
 
 
 // Neighbour offset (ex, ey, ez) in {-1,0,1}^3 -> coefficient slot.
@@ -91,7 +100,7 @@ struct SubDesc {
   long long lca_off;     // offset of the local coefficient array (27 * sx*sy*sz)
   long long y_off;       // offset of the local solution buffer (sz * P * s)  [in units of P*s]
   long long t_off;       // offset of the scratch plane (P*P) used while factoring
-  long long tv_off;      // offset of the plane right-hand side (P rows of pad16(s) columns)
+  long long tv_off;      // first plane row of the plane right-hand side (P rows)
 };
 
 // ------------------------------------------------------------- launchers --
