@@ -49,6 +49,8 @@
 #ifndef ORAS_H
 #define ORAS_H
 
+#include <stddef.h>
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -293,6 +295,22 @@ oras_status oras_blr_ranks(oras_ctx ctx, int sub, int plane, int* ranks_host, in
  * Internal staging buffers are allocated by the context and kept. */
 oras_status oras_apply_A(oras_ctx ctx, const void* x_dev, void* y_dev, int nrhs, int prec);
 oras_status oras_apply_M(oras_ctx ctx, const void* x_dev, void* y_dev, int nrhs);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): oras_apply_A
+ * with no allocation.  Same arguments, checks, kernels and results as
+ * oras_apply_A (y_dev is written with y = A x, bitwise equal to it); the
+ * staging it needs (x and y in the internal layout, and x rounded to complex64
+ * for ORAS_C64: 16 + 16 (+ 8) bytes per node and padded right-hand side,
+ * right-hand sides padded to a multiple of 8) lives in a fixed device array of
+ * oras_noalloc_scratch_bytes() bytes (64 MiB) that every GPU the library runs
+ * on holds until the process ends.  A larger request returns ORAS_E_ARG before
+ * any device work.  All calls on one GPU share that GPU's array, so calls that
+ * overlap on one GPU (several streams or host threads) race; calls ordered on
+ * one stream do not. */
+oras_status oras_apply_A_noalloc(oras_ctx ctx, const void* x_dev, void* y_dev, int nrhs, int prec);
+/* Size in bytes of the fixed staging array of oras_apply_A_noalloc. */
+size_t oras_noalloc_scratch_bytes(void);
 
 /* Wall-clock seconds of the last oras_assemble and of the last
  * oras_factor_subdomains (the paper's set-up time T_f, sec. 3.2). */

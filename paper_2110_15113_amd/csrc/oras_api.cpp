@@ -435,6 +435,15 @@ oras_status apply_A_staged(oras_ctx c, const void* x_dev, void* y_dev, int nrhs,
   return ORAS_OK;
 }
 
+size_t apply_A_scratch_bytes(oras_ctx c, int nrhs, int prec) {
+  const size_t ns = (size_t)(c->n * pad_s(nrhs));
+  return ns * (2 * sizeof(double2) + (prec == ORAS_C64 ? sizeof(float2) : 0));
+}
+
+oras_status set_error(oras_ctx c, oras_status st, const char* msg) { return fail(c, st, msg); }
+
+int ctx_device(oras_ctx c) { return c->device; }
+
 }  // namespace oras
 
 extern "C" {
@@ -459,6 +468,9 @@ oras_status oras_create(oras_ctx* out, int device, void* hip_stream) {
       delete c;
       return ORAS_E_HIP;
     }
+    // address of this device's copy of the no-alloc scratch (once per device;
+    // a failure is kept and reported by the no-alloc entry point)
+    oras::noalloc_init(device);
   }
   *out = c;
   return ORAS_OK;

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
+#include <string>
 #include <vector>
 
 #include "../../include/oras.h"
@@ -273,5 +274,13 @@ oras_status check_apply_A(oras_ctx c, const void* x_dev, const void* y_dev, int 
 // complex128) and, for prec ORAS_C64, x rounded to complex64 in x32
 oras_status apply_A_staged(oras_ctx c, const void* x_dev, void* y_dev, int nrhs, int prec,
                            double2* xin, double2* yout, float2* x32);
+// staging bytes of apply_A_staged for nrhs right-hand sides in precision prec
+size_t apply_A_scratch_bytes(oras_ctx c, int nrhs, int prec);
+oras_status set_error(oras_ctx c, oras_status st, const char* msg);
+int ctx_device(oras_ctx c);
+// Records the address of `device`'s copy of the no-alloc scratch array
+// (noalloc.hip); the device must be current.  Called once per context
+// creation, does the lookup once per device.
+oras_status noalloc_init(int device);
 
 }  // namespace oras

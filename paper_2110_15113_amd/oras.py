@@ -111,6 +111,8 @@ SIGNATURES = {
                                          ct.POINTER(BlrInfo)]),
     "oras_blr_ranks": (ct.c_int, [ct.c_void_p, ct.c_int, ct.c_int, ct.c_void_p, ct.c_int,
                                   ct.POINTER(ct.c_int)]),
+    "oras_apply_A_noalloc": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_int]),
+    "oras_noalloc_scratch_bytes": (ct.c_size_t, []),
 }
 
 
@@ -348,6 +350,14 @@ class Solver:
         _need(x, torch.complex128, self.device, (x.shape[0],) + self.shape, name="x")
         y = torch.empty_like(x)
         self._check(lib().oras_apply_A(self._ctx, _ptr(x), _ptr(y), x.shape[0], int(prec)))
+        return y
+
+    def apply_A_noalloc(self, x: torch.Tensor, y: torch.Tensor, prec: int = C128) -> torch.Tensor:
+        """y = A x into the caller's y with no device allocation (the staging
+        lives in the library's fixed per-device scratch array)."""
+        _need(x, torch.complex128, self.device, (x.shape[0],) + self.shape, name="x")
+        _need(y, torch.complex128, self.device, x.shape, name="y")
+        self._check(lib().oras_apply_A_noalloc(self._ctx, _ptr(x), _ptr(y), x.shape[0], int(prec)))
         return y
 
     def apply_M(self, x: torch.Tensor) -> torch.Tensor:
