@@ -25,6 +25,9 @@ Modules
                     least-squares misfit w.r.t. squared slowness (sec. 4 / FWI
                     motivation)
   metrics        -- the paper's gain-weighted l1 error Err (eq. eqerror)
+  pivots         -- pivots of the plane Schur complements of a local matrix
+                    without row exchanges, their ratio to the plane's largest
+                    entry, and detection of a singular B_j (sec. 2.2)
 
 Parity status of every function is stated in its module docstring.
 """
