@@ -312,6 +312,21 @@ oras_status oras_apply_A_noalloc(oras_ctx ctx, const void* x_dev, void* y_dev, i
 /* Size in bytes of the fixed staging array of oras_apply_A_noalloc. */
 size_t oras_noalloc_scratch_bytes(void);
 
+/* Pivot statistics of the last oras_factor_subdomains (sec. 2.2: the local
+ * matrices are factorised once at set-up).  The plane Schur complements S_k
+ * are inverted without row exchanges, so the smallest pivot relative to the
+ * plane's largest entry,
+ *     r = min |pivot of S_k| / max |entry of S_k|,
+ * measures how close each elimination came to breaking down (a zero or
+ * non-finite pivot already fails the factorisation with ORAS_E_NUMERIC).
+ * min_ratio receives the smallest r over all subdomain planes, sub and plane
+ * where it occurs; ratios_host (capacity doubles, may be NULL) receives r for
+ * every subdomain plane at index sub * max_planes + plane (NaN beyond a box's
+ * planes), *max_planes its second dimension.  Any output may be NULL.
+ * ORAS_E_STATE without factors, ORAS_E_ARG if capacity is too small. */
+oras_status oras_factor_stats(oras_ctx ctx, double* min_ratio, int* sub, int* plane,
+                              double* ratios_host, int capacity, int* max_planes);
+
 /* Wall-clock seconds of the last oras_assemble and of the last
  * oras_factor_subdomains (the paper's set-up time T_f, sec. 3.2). */
 oras_status oras_timings(oras_ctx ctx, double* t_assemble, double* t_factor);

@@ -86,15 +86,20 @@ __global__ void __launch_bounds__(256) schur_T_kernel(const SubDesc* subs, int k
 }
 
 // S_k = D_k - L_k T  (just D_k on the first plane), identity on the pad.
+// stats[2 (sub max_sz + k)] receives the bits of max |S_k|^2 (a non-negative
+// double, so its bits order as the value).
 template <typename R>
 __global__ void __launch_bounds__(256) build_S_kernel(const SubDesc* subs, int k, C<R>* fac,
-                                                      const C<R>* tbuf, const C<R>* lca) {
+                                                      const C<R>* tbuf, const C<R>* lca,
+                                                      unsigned long long* stats, int max_sz) {
   using T = C<R>;
+  __shared__ double red[256];
   const SubDesc sd = subs[blockIdx.z];
   if (k >= sd.sz) return;
   const int nt = sd.nt;
   const int I = blockIdx.y, J = blockIdx.x;
   if (I >= nt || J >= nt) return;
+  double big = 0.0;
   const long long P2 = (long long)sd.P * sd.P;
   T* S = fac + sd.fac_off + (long long)k * P2;
   const T* Tm = tbuf + sd.t_off;
@@ -126,9 +131,19 @@ __global__ void __launch_bounds__(256) build_S_kernel(const SubDesc* subs, int k
           }
         }
       }
+      big = fmax(big, (double)v.x * v.x + (double)v.y * v.y);
     }
     S[tile_off(I, J, nt) + e] = v;
   }
+  red[threadIdx.x] = big;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && red[0] > 0.0)
+    atomicMax(&stats[2 * ((long long)blockIdx.z * max_sz + k)],
+              (unsigned long long)__double_as_longlong(red[0]));
 }
 
 // ------------------------------------------------------- blocked Gauss-Jordan
@@ -144,9 +159,11 @@ template <> struct GjBlock<double> { static constexpr int NBT = 2, THREADS = 256
 // Gauss-Jordan.  The block lives in registers, a 4 x 4 sub-block per thread
 // ((NB / 4)^2 threads); each pivot step publishes the pivot row and column
 // through LDS, so a step costs two barriers.
+// stats[2 (sub max_sz + k) + 1] receives the bits of max 1 / |pivot|^2.
 template <typename R>
 __global__ void __launch_bounds__(GjBlock<R>::THREADS)
-gj_diag_kernel(const SubDesc* subs, int k, int kb0, C<R>* fac, int* status) {
+gj_diag_kernel(const SubDesc* subs, int k, int kb0, C<R>* fac, int* status,
+               unsigned long long* stats, int max_sz) {
   using T = C<R>;
   constexpr int NB = TILE * GjBlock<R>::NBT;
   constexpr int G = NB / 4;                  // thread grid edge
@@ -171,6 +188,7 @@ gj_diag_kernel(const SubDesc* subs, int k, int kb0, C<R>* fac, int* status) {
       for (int j = 0; j < 4; ++j) a[i][j] = blk[in_tile((r0 + i) % TILE, (c0 % TILE) + j)];
   }
   if (threadIdx.x == 0) bad = 0;
+  double inv_min = 0.0;    // largest 1 / |pivot|^2 seen (thread 0)
   for (int piv = 0; piv < nr; ++piv) {
     const int pi = piv - r0, pj = piv - c0;
     if (live) {
@@ -198,6 +216,7 @@ gj_diag_kernel(const SubDesc* subs, int k, int kb0, C<R>* fac, int* status) {
       ip.y = -p.y / d;
     }
     if (!ok && threadIdx.x == 0) bad = 1;
+    if (ok && threadIdx.x == 0 && piv < sd.p - TILE * kb0) inv_min = fmax(inv_min, 1.0 / (double)mag);
     if (live) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -226,6 +245,9 @@ gj_diag_kernel(const SubDesc* subs, int k, int kb0, C<R>* fac, int* status) {
       for (int j = 0; j < 4; ++j) blk[in_tile((r0 + i) % TILE, (c0 % TILE) + j)] = a[i][j];
   }
   if (threadIdx.x == 0 && bad) status[blockIdx.x] = 1;
+  if (threadIdx.x == 0 && inv_min > 0.0)
+    atomicMax(&stats[2 * ((long long)blockIdx.x * max_sz + k) + 1],
+              (unsigned long long)__double_as_longlong(inv_min));
 }
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -436,17 +458,19 @@ gj_update_kernel(const SubDesc* subs, int nsub, int max_nt, int k, int kb0, C<R>
 }  // namespace
 
 template <typename R>
-void launch_factor_plane(const SubDesc* subs_dev, int nsub, int k, int max_nt, C<R>* fac,
-                         C<R>* tbuf, const C<R>* lca, int* status, hipStream_t st) {
+void launch_factor_plane(const SubDesc* subs_dev, int nsub, int k, int max_nt, int max_sz,
+                         C<R>* fac, C<R>* tbuf, const C<R>* lca, int* status,
+                         unsigned long long* stats, hipStream_t st) {
   const dim3 g2(max_nt, max_nt, nsub);
   const int nsub8 = (nsub + NXCD - 1) / NXCD * NXCD;
   constexpr int NBT = GjBlock<R>::NBT;
   if (k > 0)
     hipLaunchKernelGGL((schur_T_kernel<R>), g2, dim3(256), 0, st, subs_dev, k, fac, tbuf, lca);
-  hipLaunchKernelGGL((build_S_kernel<R>), g2, dim3(256), 0, st, subs_dev, k, fac, tbuf, lca);
+  hipLaunchKernelGGL((build_S_kernel<R>), g2, dim3(256), 0, st, subs_dev, k, fac, tbuf, lca, stats,
+                     max_sz);
   for (int kb0 = 0; kb0 < max_nt; kb0 += NBT) {
     hipLaunchKernelGGL((gj_diag_kernel<R>), dim3(nsub), dim3(GjBlock<R>::THREADS), 0, st, subs_dev,
-                       k, kb0, fac, status);
+                       k, kb0, fac, status, stats, max_sz);
     hipLaunchKernelGGL((gj_rowpanel_kernel<R>), dim3(max_nt, nsub), dim3(64 * NBT), 0, st,
                        subs_dev, k, kb0, fac);
     hipLaunchKernelGGL((gj_update_kernel<R>), dim3((unsigned)(nsub8 * max_nt * max_nt)), dim3(64),
@@ -456,9 +480,9 @@ void launch_factor_plane(const SubDesc* subs_dev, int nsub, int k, int max_nt, C
   }
 }
 
-template void launch_factor_plane<float>(const SubDesc*, int, int, int, float2*, float2*,
-                                         const float2*, int*, hipStream_t);
-template void launch_factor_plane<double>(const SubDesc*, int, int, int, double2*, double2*,
-                                          const double2*, int*, hipStream_t);
+template void launch_factor_plane<float>(const SubDesc*, int, int, int, int, float2*, float2*,
+                                         const float2*, int*, unsigned long long*, hipStream_t);
+template void launch_factor_plane<double>(const SubDesc*, int, int, int, int, double2*, double2*,
+                                          const double2*, int*, unsigned long long*, hipStream_t);
 
 }  // namespace oras

@@ -77,7 +77,10 @@ struct oras_ctx_s {
   int parts[3] = {1, 1, 1};
   int overlap = 0;
   std::vector<SubDesc> subs;
-  DevBuf subs_dev, fac, tbuf, lca, status;
+  DevBuf subs_dev, fac, tbuf, lca, status, pstat;
+  std::vector<double> pivot_ratio;          // min |pivot| / max |S_k| per subdomain plane
+  double min_pivot_ratio = 0;
+  int min_pivot_sub = -1, min_pivot_plane = -1;
   OrasPlan plan;
   int max_sz = 0, max_nt = 0;
   long long max_p = 0, max_box = 0, y_rows = 0, tv_rows = 0;
@@ -125,6 +128,10 @@ struct oras_ctx_s {
     subs_dev.release(); fac.release(); tbuf.release(); lca.release();
     plan = OrasPlan();
     status.release();
+    pstat.release();
+    pivot_ratio.clear();
+    min_pivot_ratio = 0;
+    min_pivot_sub = min_pivot_plane = -1;
     ybuf.release(); tvbuf.release();
     subs.clear();
     factored = false;
@@ -417,6 +424,11 @@ oras_status check_apply_A(oras_ctx c, const void* x_dev, const void* y_dev, int 
   return check_device(c);
 }
 
+size_t apply_A_scratch_bytes(oras_ctx c, int nrhs, int prec) {
+  const size_t ns = (size_t)(c->n * pad_s(nrhs));
+  return ns * (2 * sizeof(double2) + (prec == ORAS_C64 ? sizeof(float2) : 0));
+}
+
 oras_status apply_A_staged(oras_ctx c, const void* x_dev, void* y_dev, int nrhs, int prec,
                            double2* xin, double2* yout, float2* x32) {
   const long long s = pad_s(nrhs);
@@ -433,11 +445,6 @@ oras_status apply_A_staged(oras_ctx c, const void* x_dev, void* y_dev, int nrhs,
   HIP_TRY(c, hipGetLastError());
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return ORAS_OK;
-}
-
-size_t apply_A_scratch_bytes(oras_ctx c, int nrhs, int prec) {
-  const size_t ns = (size_t)(c->n * pad_s(nrhs));
-  return ns * (2 * sizeof(double2) + (prec == ORAS_C64 ? sizeof(float2) : 0));
 }
 
 oras_status set_error(oras_ctx c, oras_status st, const char* msg) { return fail(c, st, msg); }
@@ -523,6 +530,21 @@ oras_status oras_timings(oras_ctx ctx, double* t_assemble, double* t_factor) {
   if (!ctx) return ORAS_E_ARG;
   if (t_assemble) *t_assemble = ctx->t_assemble;
   if (t_factor) *t_factor = ctx->t_factor;
+  return ORAS_OK;
+}
+
+oras_status oras_factor_stats(oras_ctx c, double* min_ratio, int* sub, int* plane,
+                              double* ratios_host, int capacity, int* max_planes) {
+  if (!c) return ORAS_E_ARG;
+  if (!c->factored) return fail(c, ORAS_E_STATE, "factor_stats before factor_subdomains");
+  if (min_ratio) *min_ratio = c->min_pivot_ratio;
+  if (sub) *sub = c->min_pivot_sub;
+  if (plane) *plane = c->min_pivot_plane;
+  if (max_planes) *max_planes = c->max_sz;
+  if (!ratios_host) return ORAS_OK;
+  if (capacity < (long long)c->pivot_ratio.size())
+    return fail(c, ORAS_E_ARG, "capacity below nsub * max_planes");
+  std::memcpy(ratios_host, c->pivot_ratio.data(), c->pivot_ratio.size() * sizeof(double));
   return ORAS_OK;
 }
 
@@ -723,9 +745,12 @@ oras_status oras_factor_subdomains_ex(oras_ctx c, const int parts[3], int overla
   TRY(dev_alloc(c, c->lca, (size_t)lca_off * cs));
   TRY(dev_alloc(c, c->subs_dev, subs.size() * sizeof(SubDesc)));
   TRY(dev_alloc(c, c->status, subs.size() * sizeof(int)));
+  const size_t nstat = 2 * subs.size() * (size_t)max_sz;
+  TRY(dev_alloc(c, c->pstat, nstat * sizeof(unsigned long long)));
   HIP_TRY(c, hipMemcpyAsync(c->subs_dev.p, subs.data(), subs.size() * sizeof(SubDesc),
                             hipMemcpyHostToDevice, c->stream));
   launch_zero(c->status.p, subs.size() * sizeof(int), c->stream);
+  launch_zero(c->pstat.p, nstat * sizeof(unsigned long long), c->stream);
   const double t0 = now();
   ifc.c_ref = c->c_ref;
   launch_assemble_local(opview(c), c->subs_dev.as<SubDesc>(), (int)subs.size(), max_box, c->lca.p,
@@ -733,13 +758,15 @@ oras_status oras_factor_subdomains_ex(oras_ctx c, const int parts[3], int overla
   HIP_TRY(c, hipGetLastError());
   for (int k = 0; k < max_sz; ++k) {
     if (factor_prec == ORAS_C64)
-      launch_factor_plane<float>(c->subs_dev.as<SubDesc>(), (int)subs.size(), k, max_nt,
+      launch_factor_plane<float>(c->subs_dev.as<SubDesc>(), (int)subs.size(), k, max_nt, max_sz,
                                  c->fac.as<float2>(), tbuf.as<float2>(), c->lca.as<float2>(),
-                                 c->status.as<int>(), c->stream);
+                                 c->status.as<int>(), c->pstat.as<unsigned long long>(),
+                                 c->stream);
     else
-      launch_factor_plane<double>(c->subs_dev.as<SubDesc>(), (int)subs.size(), k, max_nt,
+      launch_factor_plane<double>(c->subs_dev.as<SubDesc>(), (int)subs.size(), k, max_nt, max_sz,
                                   c->fac.as<double2>(), tbuf.as<double2>(), c->lca.as<double2>(),
-                                  c->status.as<int>(), c->stream);
+                                  c->status.as<int>(), c->pstat.as<unsigned long long>(),
+                                  c->stream);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
       c->release_factors();
@@ -747,7 +774,10 @@ oras_status oras_factor_subdomains_ex(oras_ctx c, const int parts[3], int overla
     }
   }
   std::vector<int> stat(subs.size(), 0);
+  std::vector<unsigned long long> pst(nstat, 0);
   HIP_TRY(c, hipMemcpyAsync(stat.data(), c->status.p, stat.size() * sizeof(int),
+                            hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(pst.data(), c->pstat.p, nstat * sizeof(unsigned long long),
                             hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->t_factor = now() - t0;
@@ -756,6 +786,23 @@ oras_status oras_factor_subdomains_ex(oras_ctx c, const int parts[3], int overla
       c->release_factors();
       return fail(c, ORAS_E_NUMERIC,
                   "zero or non-finite pivot while factoring subdomain " + std::to_string(j));
+    }
+  // min |pivot| / max |S_k| per subdomain plane (NaN beyond a box's planes)
+  c->pivot_ratio.assign(subs.size() * (size_t)max_sz, std::nan(""));
+  c->min_pivot_ratio = INFINITY;
+  for (size_t j = 0; j < subs.size(); ++j)
+    for (int k = 0; k < subs[j].sz; ++k) {
+      const size_t q = j * max_sz + k;
+      double smax2, inv2;
+      std::memcpy(&smax2, &pst[2 * q], sizeof(double));
+      std::memcpy(&inv2, &pst[2 * q + 1], sizeof(double));
+      const double r = (smax2 > 0 && inv2 > 0) ? 1.0 / std::sqrt(smax2 * inv2) : 0.0;
+      c->pivot_ratio[q] = r;
+      if (r < c->min_pivot_ratio) {
+        c->min_pivot_ratio = r;
+        c->min_pivot_sub = (int)j;
+        c->min_pivot_plane = k;
+      }
     }
   c->plane_p2_fwd.assign(max_sz, 0.0);
   c->plane_p2_bwd.assign(max_sz, 0.0);

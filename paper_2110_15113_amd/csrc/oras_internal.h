@@ -72,7 +72,6 @@ inline size_t plane_rhs_bytes(int factor_prec, long long tv_rows, long long s) {
                                  : (size_t)(tv_rows * pad16(s)) * sizeof(double2);
 }
 
-
 // Neighbour offset (ex, ey, ez) in {-1,0,1}^3 -> coefficient slot.
 __host__ __device__ constexpr inline int eidx(int ex, int ey, int ez) {
   return (ez + 1) * 9 + (ey + 1) * 3 + (ex + 1);
@@ -134,10 +133,13 @@ template <typename R>
 void launch_stencil(const C<R>* coef, const C<R>* x, const double2* b, double2* y, int nx, int ny,
                     int nz, int s, hipStream_t st);
 
-// Factorisation, one plane for all subdomains
+// Factorisation, one plane for all subdomains.  stats (2 per subdomain plane,
+// zeroed before the first plane) receives the bits of max |S_k|^2 and of
+// max 1 / |pivot|^2 (non-negative doubles, whose bits order as their values).
 template <typename R>
-void launch_factor_plane(const SubDesc* subs_dev, int nsub, int k, int max_nt, C<R>* fac,
-                         C<R>* tbuf, const C<R>* lca, int* status, hipStream_t st);
+void launch_factor_plane(const SubDesc* subs_dev, int nsub, int k, int max_nt, int max_sz,
+                         C<R>* fac, C<R>* tbuf, const C<R>* lca, int* status,
+                         unsigned long long* stats, hipStream_t st);
 
 // Shape of the ORAS apply: the 2 max_sz - 1 plane steps (forward k = 0..,
 // then backward k = max_sz - 2..0) over the subdomain descriptors.
@@ -270,12 +272,11 @@ void launch_weight_gradient(const OpView& op, const double2* qfac, const double*
 // ------------------------------------------------- shared by entry points --
 // (defined in oras_api.cpp, which owns the context layout)
 oras_status check_apply_A(oras_ctx c, const void* x_dev, const void* y_dev, int nrhs, int prec);
-// y = A x with x and y staged in the internal layout (xin, yout: n pad8(nrhs)
-// complex128) and, for prec ORAS_C64, x rounded to complex64 in x32
+// staging bytes of apply_A_staged: x and y in the internal layout (complex128)
+// plus, for prec ORAS_C64, x rounded to complex64
+size_t apply_A_scratch_bytes(oras_ctx c, int nrhs, int prec);
 oras_status apply_A_staged(oras_ctx c, const void* x_dev, void* y_dev, int nrhs, int prec,
                            double2* xin, double2* yout, float2* x32);
-// staging bytes of apply_A_staged for nrhs right-hand sides in precision prec
-size_t apply_A_scratch_bytes(oras_ctx c, int nrhs, int prec);
 oras_status set_error(oras_ctx c, oras_status st, const char* msg);
 int ctx_device(oras_ctx c);
 // Records the address of `device`'s copy of the no-alloc scratch array

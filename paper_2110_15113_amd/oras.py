@@ -111,6 +111,9 @@ SIGNATURES = {
                                          ct.POINTER(BlrInfo)]),
     "oras_blr_ranks": (ct.c_int, [ct.c_void_p, ct.c_int, ct.c_int, ct.c_void_p, ct.c_int,
                                   ct.POINTER(ct.c_int)]),
+    "oras_factor_stats": (ct.c_int, [ct.c_void_p, ct.POINTER(ct.c_double), ct.POINTER(ct.c_int),
+                                     ct.POINTER(ct.c_int), ct.c_void_p, ct.c_int,
+                                     ct.POINTER(ct.c_int)]),
     "oras_apply_A_noalloc": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_int]),
     "oras_noalloc_scratch_bytes": (ct.c_size_t, []),
 }
@@ -252,6 +255,18 @@ class Solver:
         ifc = Interface(IFACE_PML if interface == "pml" else IFACE_ROBIN, int(power), float(R0))
         self._check(lib().oras_factor_subdomains_ex(self._ctx, arr, int(overlap), int(prec),
                                                     ct.addressof(ifc)))
+
+    def factor_stats(self):
+        """(smallest min|pivot| / max|S_k| over all subdomain planes, (sub,
+        plane) where it occurs, the ratio per subdomain plane (nsub, planes))."""
+        r, j, k, mp = ct.c_double(), ct.c_int(), ct.c_int(), ct.c_int()
+        self._check(lib().oras_factor_stats(self._ctx, ct.byref(r), ct.byref(j), ct.byref(k),
+                                            None, 0, ct.byref(mp)))
+        nsub = len(self.subdomains())
+        out = np.zeros(nsub * mp.value)
+        self._check(lib().oras_factor_stats(self._ctx, None, None, None,
+                                            out.ctypes.data_as(ct.c_void_p), out.size, None))
+        return r.value, (j.value, k.value), out.reshape(nsub, mp.value)
 
     def timings(self):
         ta, tf = ct.c_double(), ct.c_double()

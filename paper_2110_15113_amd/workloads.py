@@ -185,11 +185,16 @@ def config4() -> Workload:
                     vel_start=np.full_like(vel, 2500.0))
 
 
-def config5() -> Workload:
+def config5(n: int = 160) -> Workload:
     """160^3 (4.1 M unknowns), h=20 m, 10-node PML, smooth field (ell=300 m) in
     1500-5500 m/s, Q=100, 8 Hz, 32 sources (4x8), 8x8x8 subdomains of 20^3,
-    mixed precision, restart 20, tol 1e-6."""
-    nx = ny = nz = 160
+    mixed precision, restart 20, tol 1e-6.  n < 160 draws a smaller replica
+    with the same recipe (same h, PML, frequency, velocity range, correlation
+    length, Q and source grid) and n / 20 subdomains per axis, so the owned
+    cuboids stay 20^3 (n must be a multiple of 20)."""
+    if n % 20 or n < 40:
+        raise ValueError("n must be a multiple of 20, at least 40")
+    nx = ny = nz = n
     npml = 10
     rng = _rng(5)
     f = smooth_field((nz, ny, nx), 20.0, 300.0, rng)
@@ -197,8 +202,9 @@ def config5() -> Workload:
     Q = np.full_like(vel, 100.0)
     nphys = nx - 2 * npml
     src = surface_grid(npml, nphys, nphys, 4, 8, 2)
-    return Workload("c5-random-160", nx, ny, nz, 20.0, npml, 8.0, vel, Q, src,
-                    (8, 8, 8), 2, "mixed", 1e-6, 20)
+    name = "c5-random-160" if n == 160 else f"c5-replica-{n}"
+    return Workload(name, nx, ny, nz, 20.0, npml, 8.0, vel, Q, src,
+                    (n // 20,) * 3, 2, "mixed", 1e-6, 20)
 
 
 CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}

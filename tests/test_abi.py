@@ -107,6 +107,7 @@ def test_host_only_context_validates_before_device():
         assert L.oras_compress_factors(ctx, 1e-3, 9, None) == 1
         assert L.oras_compress_factors(ctx, 1e-3, 8, None) == 2
         assert L.oras_blr_ranks(ctx, 0, 0, None, 0, None) == 2
+        assert L.oras_factor_stats(ctx, None, None, None, None, 0, None) == 2
     finally:
         L.oras_destroy(ctx)
     assert L.oras_create(None, 0, None) == 1

@@ -206,3 +206,26 @@ def test_non_finite_pivot_is_reported_and_leaves_no_factors():
     r = S.solve(S.point_sources([(4, 4, 4)]), 1e-8)
     assert r.converged.all()
     S.close()
+
+
+def test_pivot_ratio_flags_a_nearly_singular_box():
+    """With omega near zero and no PML the local matrices of interior boxes
+    approach the Neumann-only Laplacian, which is singular: the factorisation
+    still succeeds (no pivot is zero) but its pivot statistic drops by many
+    orders against the same boxes at 5 Hz with attenuation."""
+    need_gpu()
+    from paper_2110_15113_amd import oras
+    n = (12, 12, 12)
+    vel = np.full(n[::-1], 2000.0)
+    ratios = {}
+    for omega, Q in ((1e-8, None), (2 * np.pi * 5.0, np.full(n[::-1], 80.0))):
+        S = oras.Solver(0)
+        dev = S.device
+        S.assemble(torch.as_tensor(vel, device=dev), 25.0, 0, omega,
+                   None if Q is None else torch.as_tensor(Q, device=dev), prec=2)
+        S.factor((3, 3, 3), 1, 2)
+        ratios[omega] = S.factor_stats()[0]
+        S.close()
+    say(f"pivot ratio near omega 0: {ratios[1e-8]:.2e}; at 5 Hz: {ratios[2 * np.pi * 5.0]:.2e}")
+    assert ratios[1e-8] < 1e-7
+    assert ratios[2 * np.pi * 5.0] > 1e-4

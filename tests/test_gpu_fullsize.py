@@ -38,6 +38,9 @@ def _solver(w, prec):
     Q = None if w.Q is None else torch.as_tensor(w.Q, device=S.device)
     S.assemble(vel, w.h, w.npml, w.omega, Q, prec=prec)
     S.factor(w.parts, w.overlap, prec)
+    rmin, where, _ = S.factor_stats()
+    say(f"  {w.name} prec {prec}: smallest pivot / max |S_k| = {rmin:.3e} at (sub, plane) {where}")
+    assert rmin > 1e-6, rmin
     return S
 
 

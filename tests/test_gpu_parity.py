@@ -277,3 +277,42 @@ def test_gemm_accounting(prec):
                 b += cs * (p * p + 3 * p * nrhs)
     assert flops == f and nbytes == b, (flops, f, nbytes, b)
     assert secs > 0
+
+
+PIVOT_CASES = [
+    dict(n=(16, 16, 16), parts=(2, 2, 2), ov=2, npml=3, q=100.0, iface="robin"),
+    dict(n=(19, 17, 15), parts=(2, 3, 2), ov=3, npml=2, q=50.0, iface="pml"),
+]
+
+
+@pytest.mark.parametrize("case", PIVOT_CASES)
+def test_factor_pivot_ratios_match_oracle(case):
+    """The factorisation's pivot statistic min |pivot| / max |S_k| of every
+    subdomain plane (sec. 2.2, factorisation at set-up; the plane inverses
+    are formed without row exchanges) against the oracle's pivots of the
+    same Schur complements by elimination without exchanges."""
+    need_gpu()
+    from oracle import pivots
+    w = wl.small_random(case["n"], npml=case["npml"], q=case["q"], seed=21,
+                        parts=case["parts"], overlap=case["ov"])
+    say(f"pivot ratios {case}")
+    F = oracle_fields(w)
+    ref = []
+    for s in ooras.partition(case["n"], case["parts"], case["ov"]):
+        B = op.csr_from_coeffs(ooras.local_coeffs(F, s, case["iface"]))
+        sx, sy, sz = (s.hi[a] - s.lo[a] for a in range(3))
+        ref.append(pivots.plane_pivot_ratios(B, sx * sy, sz))
+    for prec, tol in ((2, 1e-9), (1, 2e-3)):
+        S = setup(w, prec=prec, parts=case["parts"], overlap=case["ov"], interface=case["iface"])
+        rmin, where, got = S.factor_stats()
+        worst = 0.0
+        for j, r in enumerate(ref):
+            g = got[j, :len(r)]
+            assert np.all(np.isnan(got[j, len(r):]))
+            worst = max(worst, float(np.max(np.abs(g - r) / r)))
+        allref = np.concatenate(ref)
+        say(f"  prec {prec}: min ratio {rmin:.3e} at {where} (oracle {allref.min():.3e}); "
+            f"largest relative gap {worst:.1e}")
+        assert worst <= tol, worst
+        assert abs(rmin - allref.min()) <= tol * allref.min()
+        S.close()
