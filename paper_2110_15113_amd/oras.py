@@ -17,7 +17,9 @@ import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboras.so")
+# ORAS_LIB selects another build of the library (the AddressSanitizer build of
+# build.py --asan); by default the one in this package folder
+LIB_PATH = os.environ.get("ORAS_LIB") or os.path.join(HERE, "liboras.so")
 
 C64 = 1
 C128 = 2
