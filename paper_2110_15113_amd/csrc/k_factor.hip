@@ -18,8 +18,9 @@
 // (the operand fragment of a 16x16x4 MFMA, and a 4x4 register block).
 //
 // The inverse is formed in place by blocked Gauss-Jordan elimination with
-// pivot blocks of several tiles (no pivoting; a zero or non-finite pivot is
-// reported):
+// pivot blocks of several tiles (no row exchanges; a zero or non-finite pivot
+// is reported, and the smallest pivot relative to the plane's largest entry
+// is recorded):
 //     A_kk <- A_kk^{-1};  A_kJ <- A_kk^{-1} A_kJ;  A_IJ <- A_IJ - A_Ik A_kJ;
 //     A_Ik <- -A_Ik A_kk^{-1}.
 // The trailing update A_IJ -= A_Ik A_kJ, which carries almost all the work,
@@ -258,51 +259,82 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 // value) walks the lane's share of the result.
 template <typename R> struct TileMma;
 
-// Complex FP32 on the 32x32x2 instruction: X rows come from the tile layout
-// (lane l: row l % 32, entries 2 (l / 32), 2 (l / 32) + 1 of each 4-column
-// run, one float4); Y is read per lane as the complex entry (k, col) and split
-// into [Br | Bi] and [-Bi | Br] by lane parity.  Real and imaginary X parts
-// accumulate separately (four independent chains).
+// Complex FP32 on the bf16 instruction (32x32x16) with exactly split operands
+// (three bf16 pieces per FP32 value, six piece products per real product:
+// FP32-level error).  The real and imaginary parts of the result are separate
+// accumulators, Re += Xr Yr - Xi Yi, Im += Xr Yi + Xi Yr.  Per 16-k half tile
+// a lane (r = l % 32, g = l / 32) holds X entries (r, 4 q + 2 g + e) of the
+// tile layout (four float4 loads, q = 0..3, e = 0..1) and the Y entries
+// (4 q + 2 g + e, r) of column r, so value i = 2 q + e of both operands refers
+// to the same k.
 template <> struct TileMma<float> {
-  f32x16 acc[2][2];
+  f32x16 accR, accI;
   __device__ void zero() {
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        acc[b][0][j] = 0.f;
-        acc[b][1][j] = 0.f;
-      }
-  }
-  __device__ void mac(const float2* __restrict__ X, const float2* __restrict__ Y) {
-    const int lane = threadIdx.x & 63, rr = lane & 31, h = lane >> 5;
-    const bool odd = (rr & 1) != 0;
-    const float4* X4 = reinterpret_cast<const float4*>(X);
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const float4 a = X4[q * 64 + rr * 2 + h];
-#pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        const float ar = e ? a.z : a.x, ai = e ? a.w : a.y;
-        const int kr = 4 * q + 2 * h + e;
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          const float2 v = Y[in_tile(kr, 16 * b + (rr >> 1))];
-          const float b1 = odd ? v.y : v.x, b2 = odd ? v.x : -v.y;
-          acc[b][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, b1, acc[b][0], 0, 0, 0);
-          acc[b][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, b2, acc[b][1], 0, 0, 0);
-        }
-      }
+    for (int j = 0; j < 16; ++j) {
+      accR[j] = 0.f;
+      accI[j] = 0.f;
     }
   }
-  // accumulator item i of lane l: row 8 (i / 4) + 4 (l / 32) + i % 4, real column l % 32
+  __device__ void mac(const float2* __restrict__ X, const float2* __restrict__ Y) {
+    const int lane = threadIdx.x & 63, rr = lane & 31, g = lane >> 5;
+    const float4* X4 = reinterpret_cast<const float4*>(X);
+    const u32x4 sgn = {0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+#pragma unroll
+    for (int hj = 0; hj < 2; ++hj) {
+      float4 a[4];
+      float2 y[8];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[q] = X4[(4 * hj + q) * 64 + rr * 2 + g];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) y[i] = Y[in_tile(16 * hj + 4 * (i >> 1) + 2 * g + (i & 1), rr)];
+      unsigned r1[4], r2[4], r3[4], i1[4], i2[4], i3[4];
+      unsigned s1[4], s2[4], s3[4], t1[4], t2[4], t3[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        split3(a[q].x, a[q].z, r1[q], r2[q], r3[q]);
+        split3(a[q].y, a[q].w, i1[q], i2[q], i3[q]);
+        split3(y[2 * q].x, y[2 * q + 1].x, s1[q], s2[q], s3[q]);
+        split3(y[2 * q].y, y[2 * q + 1].y, t1[q], t2[q], t3[q]);
+      }
+      const bf16x8 Xr1 = as_bf16x8(u32x4{r1[0], r1[1], r1[2], r1[3]});
+      const bf16x8 Xr2 = as_bf16x8(u32x4{r2[0], r2[1], r2[2], r2[3]});
+      const bf16x8 Xr3 = as_bf16x8(u32x4{r3[0], r3[1], r3[2], r3[3]});
+      const bf16x8 Xi1 = as_bf16x8(u32x4{i1[0], i1[1], i1[2], i1[3]});
+      const bf16x8 Xi2 = as_bf16x8(u32x4{i2[0], i2[1], i2[2], i2[3]});
+      const bf16x8 Xi3 = as_bf16x8(u32x4{i3[0], i3[1], i3[2], i3[3]});
+      const bf16x8 Xn1 = as_bf16x8(u32x4{i1[0], i1[1], i1[2], i1[3]} ^ sgn);
+      const bf16x8 Xn2 = as_bf16x8(u32x4{i2[0], i2[1], i2[2], i2[3]} ^ sgn);
+      const bf16x8 Xn3 = as_bf16x8(u32x4{i3[0], i3[1], i3[2], i3[3]} ^ sgn);
+      const bf16x8 Yr1 = as_bf16x8(u32x4{s1[0], s1[1], s1[2], s1[3]});
+      const bf16x8 Yr2 = as_bf16x8(u32x4{s2[0], s2[1], s2[2], s2[3]});
+      const bf16x8 Yr3 = as_bf16x8(u32x4{s3[0], s3[1], s3[2], s3[3]});
+      const bf16x8 Yi1 = as_bf16x8(u32x4{t1[0], t1[1], t1[2], t1[3]});
+      const bf16x8 Yi2 = as_bf16x8(u32x4{t2[0], t2[1], t2[2], t2[3]});
+      const bf16x8 Yi3 = as_bf16x8(u32x4{t3[0], t3[1], t3[2], t3[3]});
+#define ORAS_X3(XR, XI, XN, YR, YI)                                              \
+  accR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(XR, YR, accR, 0, 0, 0);         \
+  accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(XR, YI, accI, 0, 0, 0);         \
+  accR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(XN, YI, accR, 0, 0, 0);         \
+  accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(XI, YR, accI, 0, 0, 0);
+      ORAS_X3(Xr1, Xi1, Xn1, Yr1, Yi1)
+      ORAS_X3(Xr1, Xi1, Xn1, Yr2, Yi2)
+      ORAS_X3(Xr2, Xi2, Xn2, Yr1, Yi1)
+      ORAS_X3(Xr1, Xi1, Xn1, Yr3, Yi3)
+      ORAS_X3(Xr3, Xi3, Xn3, Yr1, Yi1)
+      ORAS_X3(Xr2, Xi2, Xn2, Yr2, Yi2)
+#undef ORAS_X3
+    }
+  }
+  // accumulator item i of lane l: row 8 (i / 4) + 4 (l / 32) + i % 4, column l % 32
   template <typename F> __device__ void visit(F f) const {
-    const int lane = threadIdx.x & 63, rr = lane & 31, h = lane >> 5;
+    const int lane = threadIdx.x & 63, rr = lane & 31, g = lane >> 5;
 #pragma unroll
-    for (int i = 0; i < 16; ++i)
-#pragma unroll
-      for (int b = 0; b < 2; ++b)
-        f(8 * (i / 4) + 4 * h + (i % 4), 16 * b + (rr >> 1), rr & 1, acc[b][0][i] + acc[b][1][i]);
+    for (int i = 0; i < 16; ++i) {
+      const int row = 8 * (i / 4) + 4 * g + (i % 4);
+      f(row, rr, 0, accR[i]);
+      f(row, rr, 1, accI[i]);
+    }
   }
 };
 

@@ -57,6 +57,39 @@ template <typename To, typename From> __host__ __device__ inline To ccast(From a
   To z; z.x = a.x; z.y = a.y; return z;
 }
 
+// ------------------------------------------- FP32 products on bf16 MFMA --
+// An FP32 value is split exactly into three bf16 pieces, x = x1 + x2 + x3,
+// each the round-to-nearest-even of what the previous pieces leave (a 24-bit
+// significand leaves at most 8 bits for the last piece).  A real product is
+// then the sum of the six piece products at least 2^-16 of the leading one
+// (a1 b1, a1 b2, a2 b1, a1 b3, a3 b1, a2 b2); the three left out are below
+// 2^-24 |a b|, so the product carries an FP32-level error on the bf16 matrix
+// instruction.
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+// Two FP32 values rounded to bf16 (round to nearest even), packed: a low, b high.
+__device__ inline unsigned pack_bf16(float a, float b) {
+  const f32x2 v = {a, b};
+  return __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2));
+}
+__device__ inline float bf16_lo(unsigned p) { return __builtin_bit_cast(float, p << 16); }
+__device__ inline float bf16_hi(unsigned p) { return __builtin_bit_cast(float, p & 0xffff0000u); }
+// a = a1 + a2 + a3 and b likewise, each piece word holding (a_i, b_i).
+__device__ inline void split3(float a, float b, unsigned& w1, unsigned& w2, unsigned& w3) {
+  w1 = pack_bf16(a, b);
+  a -= bf16_lo(w1);
+  b -= bf16_hi(w1);
+  w2 = pack_bf16(a, b);
+  a -= bf16_lo(w2);
+  b -= bf16_hi(w2);
+  w3 = pack_bf16(a, b);
+}
+__device__ inline bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+
 // ---------------------------------------------------------------- layouts --
 constexpr int TILE = 32;        // factor tile edge (complex entries)
 constexpr int RHS_ALIGN = 8;    // internal right-hand-side count granularity
@@ -126,6 +159,33 @@ void launch_pml(double2* prof, int n, int npml, double h, double omega, double c
 // ones.  out holds field_check_doubles() doubles (partials after the first two).
 long long field_check_doubles();
 void launch_field_check(const double* x, long long n, double* out, hipStream_t s);
+
+// Node fields of the matrix-free 27-point apply in the stencil precision R:
+// per node (wm_f, wm_e, wm_c, Re m~) and Im m~ (the mass weights of the
+// face, edge and corner shells and the complex squared slowness; the centre
+// weight is 1 - 6 wm_f - 12 wm_e - 8 wm_c).  The stiffness part needs only the
+// 1D PML profiles and the three family weights, which the weight table keeps
+// constant over G.
+template <typename R> struct R4;
+template <> struct R4<float> { using type = float4; };
+template <> struct R4<double> { using type = double4; };
+template <typename R> struct StencilMF {
+  const typename R4<R>::type* f4;
+  const R* fim;
+  const double2* px;     // half-grid profiles, 2 n + 1 per axis
+  const double2* py;
+  const double2* pz;
+  int lo[3], hi[3];      // nodes [lo, hi) per axis whose profile values at
+                         // offsets -1, -1/2, 0, 1/2, 1 are exactly 1
+  double W1, W2, W3;     // stiffness family weights: w1 / h^2, w2 / (8 h^2), w3 / (16 h^2)
+  double om2;            // omega^2
+};
+template <typename R>
+void launch_mass_fields(const double* w7, const double2* mt, long long n,
+                        typename R4<R>::type* f4, R* fim, hipStream_t st);
+template <typename R>
+void launch_stencil_mf(const StencilMF<R>& op, const C<R>* x, const double2* b, double2* y, int nx,
+                       int ny, int nz, int s, hipStream_t st);
 
 // Stencil: y = A x (or y = b - A x when b != null).  x precision Tx, coefficient
 // precision Tc (== Tx), output double2.
