@@ -26,7 +26,10 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"hbm_GBps": 8000.0, "fp32_mfma_TFLOPs": 157.3, "fp64_mfma_TFLOPs": 78.6}
+PEAK = {"hbm_GBps": 8000.0, "fp32_mfma_TFLOPs": 157.3, "fp64_mfma_TFLOPs": 78.6,
+        "fp32_vector_TFLOPs": 157.3, "fp64_vector_TFLOPs": 78.6,
+        # 256 CUs x 64 lanes x 2 flops x 2.4 GHz: FP32 FMAs without packed math
+        "fp32_vector_unpacked_TFLOPs": 78.6}
 
 
 def parse():
@@ -450,12 +453,20 @@ def main():
     last, ta, tf = results[-1]
     ok = bool(last.converged.all())
     iters = int(last.total_iters)
-    # 27-point apply bandwidth: x in the stencil precision, y in complex128,
-    # 27 coefficients per node in the stencil precision
+    # 27-point apply against its algorithmic bytes: x read in the stencil
+    # precision, y written in complex128 (the Arnoldi basis), and the node
+    # fields the operator is formed from (three mass weights and the complex
+    # squared slowness in the stencil precision, five values per node; the
+    # stiffness needs only the 1D PML profiles).  Its arithmetic floor: one
+    # complex multiply-add (four real FMAs, 8 flops) per node, neighbour and
+    # right-hand side on the vector ALUs.
     cb = 8 if P == oras.C64 else 16
     s_pad = (nrhs + 7) // 8 * 8
-    sten_bytes = w.n * (s_pad * (cb + 16) + 27 * cb)
+    sten_bytes = w.n * (s_pad * (cb + 16) + 5 * (cb // 2))
+    sten_flops = w.n * s_pad * 27 * 8
     sten_GBps = sten_bytes * iters / last.t_stencil / 1e9 if last.t_stencil > 0 else None
+    sten_TFLOPs = sten_flops * iters / last.t_stencil / 1e12 if last.t_stencil > 0 else None
+    vec_peak = PEAK["fp32_vector_TFLOPs"] if P == oras.C64 else PEAK["fp64_vector_TFLOPs"]
     roof = None
     if not args.no_profile:
         gs, gl, gf, gb = S.kernel_stats()
@@ -529,6 +540,11 @@ def main():
         "t_ortho_s": last.t_ortho,
         "stencil_GBps": sten_GBps,
         "stencil_hbm_frac": (sten_GBps / PEAK["hbm_GBps"]) if sten_GBps else None,
+        "stencil_fma_TFLOPs": sten_TFLOPs,
+        "stencil_fma_frac_of_vector_peak": (sten_TFLOPs / vec_peak) if sten_TFLOPs else None,
+        # FP32 is built without packed math, which halves the vector FMA rate
+        "stencil_fma_frac_of_unpacked_rate": (sten_TFLOPs / PEAK["fp32_vector_unpacked_TFLOPs"])
+        if sten_TFLOPs else None,
         "dof_RHS_per_s": w.n * nrhs * args.steps / elapsed,
         "roofline": roof,
         # the paper's own figure for its pseudo-block ORAS solve, with the

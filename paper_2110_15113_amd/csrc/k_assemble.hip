@@ -204,7 +204,7 @@ __device__ void row_coeffs(const OpView& V, const int pos[3], const int lo[3], c
   }
 }
 
-__global__ void assemble_global_kernel(OpView V, double2* coef128, float2* coef64) {
+__global__ void assemble_global_kernel(OpView V, double2* coef) {
   const long long n = (long long)V.nx * V.ny * V.nz;
   const long long node = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (node >= n) return;
@@ -217,8 +217,7 @@ __global__ void assemble_global_kernel(OpView V, double2* coef128, float2* coef6
   double2 c[27];
   row_coeffs(V, pos, lo, hi, false, c);
   for (int e = 0; e < 27; ++e) {
-    coef128[e * n + node] = c[e];
-    if (coef64) coef64[e * n + node] = make_float2((float)c[e].x, (float)c[e].y);
+    coef[e * n + node] = c[e];
   }
 }
 
@@ -379,11 +378,11 @@ __global__ void check_reduce_kernel(const double* part, int np, double* out) {
 
 }  // namespace
 
-void launch_assemble_global(const OpView& op, double2* coef128, float2* coef64, hipStream_t s) {
+void launch_assemble_global(const OpView& op, double2* coef, hipStream_t s) {
   const long long n = (long long)op.nx * op.ny * op.nz;
   const int bs = 128;
   hipLaunchKernelGGL(assemble_global_kernel, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, s,
-                     op, coef128, coef64);
+                     op, coef);
 }
 
 void launch_assemble_local(const OpView& op, const SubDesc* subs_dev, int nsub, long long max_box,

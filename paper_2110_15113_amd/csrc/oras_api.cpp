@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -67,7 +68,12 @@ struct oras_ctx_s {
   int npml = 0, free_surface = 0;
   double c_ref = 0;
   int stencil_prec = ORAS_C128;
-  DevBuf w7, mt, qf, px, py, pz, coef128, coef64, wtab, scratch8, gradw;
+  DevBuf w7, mt, qf, px, py, pz, wtab, scratch8, gradw;
+  // node fields of the matrix-free apply, per stencil precision; nodes
+  // [mf_lo, mf_hi) per axis lie where every profile value they use is 1
+  DevBuf mf4_64, mfim_64, mf4_32, mfim_32, mffac64, mffac32, mftiles;
+  int mf_lo[3] = {0, 0, 0}, mf_hi[3] = {0, 0, 0};
+  int mf_ntiles = 0, mf_nplain = 0;
   bool weights_match_m = false;   // the stencil weights are those of the current m
   double t_assemble = 0;
 
@@ -146,7 +152,9 @@ struct oras_ctx_s {
     release_factors();
     release_workspace();
     w7.release(); mt.release(); qf.release(); px.release(); py.release(); pz.release();
-    coef128.release(); coef64.release(); wtab.release(); scratch8.release(); gradw.release();
+    mf4_64.release(); mfim_64.release(); mf4_32.release(); mfim_32.release();
+    mffac64.release(); mffac32.release(); mftiles.release();
+    wtab.release(); scratch8.release(); gradw.release();
     assembled = false;
   }
 };
@@ -238,12 +246,115 @@ long long pad_s(int nrhs) { return ((long long)nrhs + RHS_ALIGN - 1) / RHS_ALIGN
 
 size_t csize(int prec) { return prec == ORAS_C64 ? sizeof(float2) : sizeof(double2); }
 
-oras_status build_coefficients(oras_ctx c) {
-  const OpView op = opview(c);
-  launch_assemble_global(op, c->coef128.as<double2>(),
-                         c->stencil_prec == ORAS_C64 ? c->coef64.as<float2>() : nullptr, c->stream);
+// Nodes [lo, hi) of one axis whose profile values at offsets -1 .. 1 (half
+// grid indices 2 i - 1 .. 2 i + 3, clamped as the apply clamps them) are
+// exactly 1; lo = hi = 0 when they do not form one interval.
+void plain_range(const std::vector<double2>& p, int n, int& lo, int& hi) {
+  auto plain = [&](int i) {
+    for (int t = 2 * i - 1; t <= 2 * i + 3; ++t) {
+      const double2 v = p[std::min(std::max(t, 0), 2 * n)];
+      if (v.x != 1.0 || v.y != 0.0) return false;
+    }
+    return true;
+  };
+  lo = 0;
+  while (lo < n && !plain(lo)) ++lo;
+  hi = lo;
+  while (hi < n && plain(hi)) ++hi;
+  for (int i = hi; i < n; ++i)
+    if (plain(i)) { lo = hi = 0; return; }
+  if (lo == hi) lo = hi = 0;
+}
+
+// Node fields of the matrix-free apply from w7 and m~ (both precisions the
+// context applies A in: always FP64, for the true residual, and FP32 when the
+// stencil runs in single precision), and the PML-free node ranges.
+oras_status build_fields(oras_ctx c) {
+  launch_mass_fields<double>(c->w7.as<double>(), c->mt.as<double2>(), c->n,
+                             c->mf4_64.as<double4>(), c->mfim_64.as<double>(), c->stream);
+  if (c->stencil_prec == ORAS_C64)
+    launch_mass_fields<float>(c->w7.as<double>(), c->mt.as<double2>(), c->n,
+                              c->mf4_32.as<float4>(), c->mfim_32.as<float>(), c->stream);
   HIP_TRY(c, hipGetLastError());
+  // per-axis factor tables, 9 per node coordinate: R(d), H(d), N(d), d = -1, 0, 1
+  const int ns[3] = {c->nx, c->ny, c->nz};
+  const DevBuf* ps[3] = {&c->px, &c->py, &c->pz};
+  std::vector<double2> fac64;
+  for (int a = 0; a < 3; ++a) {
+    std::vector<double2> p((size_t)(2 * ns[a] + 1));
+    HIP_TRY(c, hipMemcpyAsync(p.data(), ps[a]->p, p.size() * sizeof(double2),
+                              hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    plain_range(p, ns[a], c->mf_lo[a], c->mf_hi[a]);
+    auto at = [&](int t) {
+      const double2 v = p[std::min(std::max(t, 0), 2 * ns[a])];
+      return std::complex<double>(v.x, v.y);
+    };
+    for (int i = 0; i < ns[a]; ++i) {
+      const std::complex<double> hm = at(2 * i), hp = at(2 * i + 2);
+      const std::complex<double> f[9] = {1.0 / hm, 1.0 / hm + 1.0 / hp, 1.0 / hp,
+                                         hm, hm + hp, hp,
+                                         at(2 * i - 1), at(2 * i + 1), at(2 * i + 3)};
+      for (const auto& z : f) fac64.push_back(make_double2(z.real(), z.imag()));
+    }
+  }
+  TRY(dev_alloc(c, c->mffac64, fac64.size() * sizeof(double2)));
+  HIP_TRY(c, hipMemcpyAsync(c->mffac64.p, fac64.data(), fac64.size() * sizeof(double2),
+                            hipMemcpyHostToDevice, c->stream));
+  if (c->stencil_prec == ORAS_C64) {
+    std::vector<float2> fac32(fac64.size());
+    for (size_t i = 0; i < fac64.size(); ++i)
+      fac32[i] = make_float2((float)fac64[i].x, (float)fac64[i].y);
+    TRY(dev_alloc(c, c->mffac32, fac32.size() * sizeof(float2)));
+    HIP_TRY(c, hipMemcpyAsync(c->mffac32.p, fac32.data(), fac32.size() * sizeof(float2),
+                              hipMemcpyHostToDevice, c->stream));
+  }
+  std::vector<int> tiles;
+  stencil_mf_tiles(c->mf_lo, c->mf_hi, c->nx, c->ny, c->nz, tiles, c->mf_nplain);
+  c->mf_ntiles = (int)(tiles.size() / 4);
+  TRY(dev_alloc(c, c->mftiles, tiles.size() * sizeof(int)));
+  HIP_TRY(c, hipMemcpyAsync(c->mftiles.p, tiles.data(), tiles.size() * sizeof(int),
+                            hipMemcpyHostToDevice, c->stream));
+  // the host tables must outlive the copies
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
   return ORAS_OK;
+}
+
+template <typename R> StencilMF<R> mf_view(oras_ctx c);
+template <> StencilMF<double> mf_view<double>(oras_ctx c) {
+  StencilMF<double> v;
+  v.f4 = c->mf4_64.as<double4>();
+  v.fim = c->mfim_64.as<double>();
+  v.fx = c->mffac64.as<double2>();
+  return v;
+}
+template <> StencilMF<float> mf_view<float>(oras_ctx c) {
+  StencilMF<float> v;
+  v.f4 = c->mf4_32.as<float4>();
+  v.fim = c->mfim_32.as<float>();
+  v.fx = c->mffac32.as<float2>();
+  return v;
+}
+
+// y (internal [n][s] c128) = A x, or b - A x when b is given, with x in the
+// stencil precision R
+template <typename R>
+void apply_stencil(oras_ctx c, const C<R>* x, const double2* b, double2* y, int s, hipStream_t st) {
+  StencilMF<R> v = mf_view<R>(c);
+  v.fy = v.fx + 9 * c->nx;
+  v.fz = v.fy + 9 * c->ny;
+  v.tiles = c->mftiles.as<int4>();
+  v.ntiles = c->mf_ntiles;
+  v.nplain = c->mf_nplain;
+  const Table& t = weight_table();
+  const double ih2 = 1.0 / (c->h * c->h);
+  // family weights (the same in every row of the table) with the averaging
+  // factors of the in-plane (1/2 x 1/4) and cube-centre (1/16) differences
+  v.W1 = t.w[0] * ih2;
+  v.W2 = t.w[1] * ih2 * 0.125;
+  v.W3 = t.w[2] * ih2 * 0.0625;
+  v.om2 = c->omega * c->omega;
+  launch_stencil_mf<R>(v, x, b, y, c->nx, c->ny, c->nz, s, st);
 }
 
 int nblk_for(long long n) {
@@ -257,10 +368,9 @@ oras_status stencil_internal(oras_ctx c, const double2* x, const double2* b, dou
   if (prec == ORAS_C64) {
     TRY(dev_alloc(c, c->Tmp64, (size_t)c->n * s * sizeof(float2)));
     launch_cast<float>(x, c->Tmp64.as<float2>(), c->n * s, c->stream);
-    launch_stencil<float>(c->coef64.as<float2>(), c->Tmp64.as<float2>(), b, y, c->nx, c->ny, c->nz,
-                          s, c->stream);
+    apply_stencil<float>(c, c->Tmp64.as<float2>(), b, y, s, c->stream);
   } else {
-    launch_stencil<double>(c->coef128.as<double2>(), x, b, y, c->nx, c->ny, c->nz, s, c->stream);
+    apply_stencil<double>(c, x, b, y, s, c->stream);
   }
   HIP_TRY(c, hipGetLastError());
   return ORAS_OK;
@@ -435,11 +545,9 @@ oras_status apply_A_staged(oras_ctx c, const void* x_dev, void* y_dev, int nrhs,
   launch_to_internal((const double2*)x_dev, xin, c->n, nrhs, (int)s, 0, c->stream);
   if (prec == ORAS_C64) {
     launch_cast<float>(xin, x32, c->n * s, c->stream);
-    launch_stencil<float>(c->coef64.as<float2>(), x32, nullptr, yout, c->nx, c->ny, c->nz,
-                          (int)s, c->stream);
+    apply_stencil<float>(c, x32, nullptr, yout, (int)s, c->stream);
   } else {
-    launch_stencil<double>(c->coef128.as<double2>(), xin, nullptr, yout, c->nx, c->ny, c->nz,
-                           (int)s, c->stream);
+    apply_stencil<double>(c, xin, nullptr, yout, (int)s, c->stream);
   }
   launch_from_internal(yout, (double2*)y_dev, c->n, nrhs, (int)s, 0, c->stream);
   HIP_TRY(c, hipGetLastError());
@@ -572,10 +680,10 @@ oras_status oras_assemble(oras_ctx c, const oras_grid* g, const double* vel_dev,
   double vmax = 0;
   TRY(check_field(c, vel_dev, n, "velocity", &vmax));
   if (q_dev) TRY(check_field(c, q_dev, n, "Q", nullptr));
-  const double need = (double)n * (7 * 8 + 16 * 2 + 27 * 16 + (stencil_prec == ORAS_C64 ? 27 * 8 : 0));
+  const double need = (double)n * (7 * 8 + 16 * 2 + 40 + (stencil_prec == ORAS_C64 ? 20 : 0));
   {
-    const double held = (double)(c->w7.bytes + c->mt.bytes + c->qf.bytes + c->coef128.bytes +
-                                 c->coef64.bytes);
+    const double held = (double)(c->w7.bytes + c->mt.bytes + c->qf.bytes + c->mf4_64.bytes +
+                                 c->mfim_64.bytes + c->mf4_32.bytes + c->mfim_32.bytes);
     TRY(check_free(c, need - held));
   }
   // buffers of an earlier assembly are reused when large enough; the factors
@@ -599,8 +707,12 @@ oras_status oras_assemble(oras_ctx c, const oras_grid* g, const double* vel_dev,
   TRY(dev_alloc(c, c->px, (size_t)(2 * g->nx + 1) * sizeof(double2)));
   TRY(dev_alloc(c, c->py, (size_t)(2 * g->ny + 1) * sizeof(double2)));
   TRY(dev_alloc(c, c->pz, (size_t)(2 * g->nz + 1) * sizeof(double2)));
-  TRY(dev_alloc(c, c->coef128, (size_t)n * 27 * sizeof(double2)));
-  if (stencil_prec == ORAS_C64) TRY(dev_alloc(c, c->coef64, (size_t)n * 27 * sizeof(float2)));
+  TRY(dev_alloc(c, c->mf4_64, (size_t)n * sizeof(double4)));
+  TRY(dev_alloc(c, c->mfim_64, (size_t)n * sizeof(double)));
+  if (stencil_prec == ORAS_C64) {
+    TRY(dev_alloc(c, c->mf4_32, (size_t)n * sizeof(float4)));
+    TRY(dev_alloc(c, c->mfim_32, (size_t)n * sizeof(float)));
+  }
   TRY(dev_alloc(c, c->wtab, t.w.size() * sizeof(double)));
   HIP_TRY(c, hipMemcpyAsync(c->wtab.p, t.w.data(), t.w.size() * sizeof(double),
                             hipMemcpyHostToDevice, c->stream));
@@ -615,7 +727,7 @@ oras_status oras_assemble(oras_ctx c, const oras_grid* g, const double* vel_dev,
   launch_pml(c->pz.as<double2>(), c->nz, c->npml, c->h, omega, c->c_ref, pml->R0, pml->power,
              c->free_surface ? 0 : 1, 1, c->stream);
   HIP_TRY(c, hipGetLastError());
-  TRY(build_coefficients(c));
+  TRY(build_fields(c));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->assembled = true;
   c->weights_match_m = true;
@@ -640,7 +752,7 @@ oras_status oras_set_m_ex(oras_ctx c, const double* m_dev, int flags) {
                 c->stream, follow ? 0 : 1);
   c->weights_match_m = follow;
   HIP_TRY(c, hipGetLastError());
-  TRY(build_coefficients(c));
+  TRY(build_fields(c));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return ORAS_OK;
 }
@@ -1212,8 +1324,9 @@ oras_status oras_coefficients(oras_ctx c, void* out_dev) {
   if (!out_dev) return fail(c, ORAS_E_ARG, "null output");
   if (!c->assembled) return fail(c, ORAS_E_STATE, "coefficients before assemble");
   TRY(check_device(c));
-  HIP_TRY(c, hipMemcpyAsync(out_dev, c->coef128.p, (size_t)c->n * 27 * sizeof(double2),
-                            hipMemcpyDeviceToDevice, c->stream));
+  // assembled on demand: the apply itself forms them from the node fields
+  launch_assemble_global(opview(c), (double2*)out_dev, c->stream);
+  HIP_TRY(c, hipGetLastError());
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return ORAS_OK;
 }
@@ -1359,16 +1472,14 @@ oras_status oras_solve(oras_ctx c, const void* b_dev, void* x_dev, int nrhs, dou
           launch_cast<float>((const double2*)Zj, c->Tmp64.as<float2>(), ns, st);
           zin = c->Tmp64.as<float2>();
         }
-        launch_stencil<float>(c->coef64.as<float2>(), zin, nullptr, Vn, c->nx, c->ny, c->nz,
-                              (int)s, st);
+        apply_stencil<float>(c, zin, nullptr, Vn, (int)s, st);
       } else {
         const double2* zin = (const double2*)Zj;
         if (convert) {
           launch_widen((const float2*)Zj, c->Tmp.as<double2>(), ns, st);
           zin = c->Tmp.as<double2>();
         }
-        launch_stencil<double>(c->coef128.as<double2>(), zin, nullptr, Vn, c->nx, c->ny, c->nz,
-                               (int)s, st);
+        apply_stencil<double>(c, zin, nullptr, Vn, (int)s, st);
       }
       HIP_TRY(c, hipEventRecord(ev[2], st));
       launch_cgs_dot(V, ns, j + 1, Vn, n, (int)s, dpart, nblk, st);

@@ -138,7 +138,7 @@ struct SubDesc {
 
 // ------------------------------------------------------------- launchers --
 // Assembly
-void launch_assemble_global(const OpView& op, double2* coef128, float2* coef64, hipStream_t s);
+void launch_assemble_global(const OpView& op, double2* coef, hipStream_t s);
 // Interface condition of the local matrices (kind ORAS_IFACE_ROBIN or
 // ORAS_IFACE_PML; the PML layer law uses c_ref, R0 and power).
 struct IfaceView {
@@ -165,33 +165,36 @@ void launch_field_check(const double* x, long long n, double* out, hipStream_t s
 // face, edge and corner shells and the complex squared slowness; the centre
 // weight is 1 - 6 wm_f - 12 wm_e - 8 wm_c).  The stiffness part needs only the
 // 1D PML profiles and the three family weights, which the weight table keeps
-// constant over G.
+// constant over G; the profiles enter through per-axis factor tables, nine
+// complex values per node coordinate i: R(d), H(d), N(d) for d = -1, 0, +1
+// with R(+-1) = 1 / s(i +- 1/2), H(+-1) = s(i +- 1/2), R(0) and H(0) the sums
+// of the two, N(d) = s(i + d) (half-grid indices clamped to the profile).
 template <typename R> struct R4;
 template <> struct R4<float> { using type = float4; };
 template <> struct R4<double> { using type = double4; };
 template <typename R> struct StencilMF {
   const typename R4<R>::type* f4;
   const R* fim;
-  const double2* px;     // half-grid profiles, 2 n + 1 per axis
-  const double2* py;
-  const double2* pz;
-  int lo[3], hi[3];      // nodes [lo, hi) per axis whose profile values at
-                         // offsets -1, -1/2, 0, 1/2, 1 are exactly 1
+  const C<R>* fx;        // factor tables, 9 per node coordinate along each axis
+  const C<R>* fy;
+  const C<R>* fz;
+  const int4* tiles;     // tiles (i0, j0, k0, k1), PML-free ones first (stencil_mf_tiles)
+  int ntiles, nplain;
   double W1, W2, W3;     // stiffness family weights: w1 / h^2, w2 / (8 h^2), w3 / (16 h^2)
   double om2;            // omega^2
 };
 template <typename R>
 void launch_mass_fields(const double* w7, const double2* mt, long long n,
                         typename R4<R>::type* f4, R* fim, hipStream_t st);
+// The apply's tiles as (i0, j0, k0, k1) quadruples, the nplain PML-free ones
+// first (every node within [lo, hi) per axis: all profile values its row
+// uses are 1), then the PML tiles covering the rest of the grid.
+void stencil_mf_tiles(const int lo[3], const int hi[3], int nx, int ny, int nz,
+                      std::vector<int>& tiles, int& nplain);
 template <typename R>
 void launch_stencil_mf(const StencilMF<R>& op, const C<R>* x, const double2* b, double2* y, int nx,
                        int ny, int nz, int s, hipStream_t st);
 
-// Stencil: y = A x (or y = b - A x when b != null).  x precision Tx, coefficient
-// precision Tc (== Tx), output double2.
-template <typename R>
-void launch_stencil(const C<R>* coef, const C<R>* x, const double2* b, double2* y, int nx, int ny,
-                    int nz, int s, hipStream_t st);
 
 // Factorisation, one plane for all subdomains.  stats (2 per subdomain plane,
 // zeroed before the first plane) receives the bits of max |S_k|^2 and of
