@@ -39,13 +39,38 @@ __global__ void from_internal_kernel(const double2* __restrict__ src, double2* _
   dst[idx] = v;
 }
 
+// Sum over the lanes of a 64-lane wave that share lane % s (s a power of
+// two): a butterfly over the lane offsets >= s, fixed order, no barrier.
+// Lane l < s of the wave holds the sum (every lane does, in some order).
+__device__ inline double wave_sum_stride(double v, int s) {
+  for (int o = 32; o >= s; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// The threads of a work-group that share a column (thread t holds column
+// t % s) meet in one wave at power-of-two lane distances when s is a power of
+// two below 64 (the work-group is then 256 threads).
+__device__ inline bool wave_columns(int s) { return s < 64 && (s & (s - 1)) == 0; }
+
+// Column sums of a work-group whose thread t holds column t % s, G groups of
+// s threads: wave butterflies and the waves' sums in wave order through LDS
+// when the columns meet in waves, else the G group sums in order.
 __device__ inline void block_reduce_store(double* lds, double v, int s, int G, double* out) {
   const int tid = threadIdx.x;
-  lds[tid] = v;
+  if (wave_columns(s)) {
+    v = wave_sum_stride(v, s);
+    if ((tid & 63) < s) lds[(tid >> 6) * s + (tid & 63)] = v;
+  } else {
+    lds[tid] = v;
+  }
   __syncthreads();
   if (tid < s) {
     double acc = 0.0;
-    for (int g = 0; g < G; ++g) acc += lds[g * s + tid];
+    if (wave_columns(s)) {
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) acc += lds[w * s + tid];
+    } else {
+      for (int g = 0; g < G; ++g) acc += lds[g * s + tid];
+    }
     *out = acc;
   }
   __syncthreads();
@@ -64,16 +89,14 @@ __global__ void colnorm2_kernel(const double2* __restrict__ x, long long n, int 
   block_reduce_store(lds, acc, s, G, partial + (long long)blockIdx.x * s + c);
 }
 
-// Fixed-order tree sum of 256 per-thread values (deterministic).
+// Fixed-order sum of 256 per-thread values (deterministic): a butterfly
+// within each 64-lane wave, then the four wave sums in order through LDS.
 __device__ inline double tree_sum(double* lds, double v) {
+  v = wave_sum_stride(v, 1);
   __syncthreads();   // earlier readers of lds are done
-  lds[threadIdx.x] = v;
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) lds[threadIdx.x] += lds[threadIdx.x + w];
-    __syncthreads();
-  }
-  return lds[0];
+  return (lds[0] + lds[1]) + (lds[2] + lds[3]);
 }
 
 // out[c] = sqrt(sum over blocks of partial[blk][c]); one work-group per column
@@ -92,8 +115,8 @@ __global__ void __launch_bounds__(256) finish_norm_kernel(const double* __restri
 __global__ void cgs_dot_kernel(const double2* __restrict__ V, long long vstride, int j1,
                                const double2* __restrict__ w, long long n, int s,
                                double2* __restrict__ partial) {
-  __shared__ double lre[256];
-  __shared__ double lim[256];
+  __shared__ double lre[8 * 256];
+  __shared__ double lim[8 * 256];
   const int G = blockDim.x / s;
   const int c = threadIdx.x % s, g = threadIdx.x / s;
   for (int i0 = 0; i0 < j1; i0 += 8) {
@@ -108,23 +131,44 @@ __global__ void cgs_dot_kernel(const double2* __restrict__ V, long long vstride,
       for (int ii = 0; ii < 8; ++ii)
         if (ii < cnt) cfmaconj(acc[ii], V[(long long)(i0 + ii) * vstride + node * s + c], wv);
     }
+    // column sums of the cnt basis vectors behind one barrier: butterflies
+    // within each wave and the waves in order when the columns meet in
+    // waves, else the G group sums in order
+    const bool wc = wave_columns(s);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int ii = 0; ii < 8; ++ii) {
       if (ii < cnt) {
-        lre[threadIdx.x] = acc[ii].x;
-        lim[threadIdx.x] = acc[ii].y;
-        __syncthreads();
-        if (threadIdx.x < s) {
-          double2 t = make_double2(0.0, 0.0);
-          for (int q = 0; q < G; ++q) {
-            t.x += lre[q * s + threadIdx.x];
-            t.y += lim[q * s + threadIdx.x];
+        if (wc) {
+          const double re = wave_sum_stride(acc[ii].x, s), im = wave_sum_stride(acc[ii].y, s);
+          if (lane < s) {
+            lre[(ii * 4 + wave) * s + lane] = re;
+            lim[(ii * 4 + wave) * s + lane] = im;
           }
-          partial[((long long)blockIdx.x * j1 + i0 + ii) * s + threadIdx.x] = t;
+        } else {
+          lre[ii * 256 + threadIdx.x] = acc[ii].x;
+          lim[ii * 256 + threadIdx.x] = acc[ii].y;
         }
-        __syncthreads();
       }
     }
+    __syncthreads();
+    for (int q = threadIdx.x; q < cnt * s; q += blockDim.x) {
+      const int ii = q / s, cc = q % s;
+      double2 t = make_double2(0.0, 0.0);
+      if (wc) {
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+          t.x += lre[(ii * 4 + w) * s + cc];
+          t.y += lim[(ii * 4 + w) * s + cc];
+        }
+      } else {
+        for (int g = 0; g < G; ++g) {
+          t.x += lre[ii * 256 + g * s + cc];
+          t.y += lim[ii * 256 + g * s + cc];
+        }
+      }
+      partial[((long long)blockIdx.x * j1 + i0 + ii) * s + cc] = t;
+    }
+    __syncthreads();
   }
 }
 
