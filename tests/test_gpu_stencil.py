@@ -28,6 +28,7 @@ CASES = [
     dict(n=(40, 36, 26), npml=3, q=80.0, nrhs=1, seed=31),    # PML and interior tiles
     dict(n=(37, 20, 19), npml=2, q=None, nrhs=13, seed=32),   # ragged tiles, 2 chunks
     dict(n=(21, 18, 11), npml=0, q=50.0, nrhs=40, seed=33),   # no PML: interior tiles only
+    dict(n=(33, 17, 21), npml=2, q=70.0, nrhs=50, seed=37),   # chunks of 32, 16 and 8 RHS
 ]
 
 
