@@ -157,6 +157,7 @@ plane_rhs_x3_kernel(const SubDesc* __restrict__ subs, int nsub, int nrb, int ncc
                     u32x4* __restrict__ tp, const double2* __restrict__ v,
                     const double* __restrict__ scale, int nx, int ny, int s, int s32) {
   __shared__ float2 tile[RB_ROWS][33];
+  __shared__ float2 cpl[9][RB_ROWS];   // the block rows' couplings to plane k -+ 1
   int sub, item;
   xcd_map(nrb * ncc, sub, item);
   if (sub >= nsub) return;
@@ -169,6 +170,25 @@ plane_rhs_x3_kernel(const SubDesc* __restrict__ subs, int nsub, int nrb, int ncc
   const int rl = tid >> 3, cp = tid & 7;
   const int q = q0 + rl;
   const int c = 32 * cc + 4 * cp;
+  const bool couple = bwd || k > 0;
+  // each coupling is loaded once per block instead of once per column group
+  if (couple) {
+    const long long nbox = (long long)sd.sx * sd.sy * sd.sz;
+    const int ez = bwd ? 1 : -1;
+    const float sg = bwd ? 1.f : -1.f;
+    for (int i = tid; i < 9 * RB_ROWS; i += RB_THREADS) {
+      const int e = i / RB_ROWS, r = i % RB_ROWS, qq = q0 + r;
+      float2 l = make_float2(0.f, 0.f);
+      if (qq < sd.p) {
+        const long long node = ((long long)k * sd.sy + qq / sd.sx) * sd.sx + qq % sd.sx;
+        l = lca[sd.lca_off + eidx(e % 3 - 1, e / 3 - 1, ez) * nbox + node];
+        l.x *= sg;
+        l.y *= sg;
+      }
+      cpl[e][r] = l;
+    }
+    __syncthreads();
+  }
   float2 t[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) t[j] = make_float2(0.f, 0.f);
@@ -183,22 +203,15 @@ plane_rhs_x3_kernel(const SubDesc* __restrict__ subs, int nsub, int nrb, int ncc
         t[j] = make_float2((float)(vj.x * sj), (float)(vj.y * sj));
       }
     }
-    if (bwd || k > 0) {
-      const long long nbox = (long long)sd.sx * sd.sy * sd.sz;
-      const long long node = ((long long)k * sd.sy + qy) * sd.sx + qx;
-      const float2* L = lca + sd.lca_off;
+    if (couple) {
       const float2* Yn = ybuf + (sd.y_off + (long long)(bwd ? k + 1 : k - 1) * sd.P) * s + c;
-      const int ez = bwd ? 1 : -1;
-      const float sg = bwd ? 1.f : -1.f;
 #pragma unroll
       for (int dy = -1; dy <= 1; ++dy) {
         const int py = min(max(qy + dy, 0), sd.sy - 1);
 #pragma unroll
         for (int dx = -1; dx <= 1; ++dx) {
           const int px = min(max(qx + dx, 0), sd.sx - 1);
-          float2 l = L[eidx(dx, dy, ez) * nbox + node];
-          l.x *= sg;
-          l.y *= sg;
+          const float2 l = cpl[(dy + 1) * 3 + dx + 1][rl];
           const float4* yp = reinterpret_cast<const float4*>(Yn + (long long)(py * sd.sx + px) * s);
           const float4 y0 = yp[0], y1 = yp[1];
           cfma(t[0], l, make_float2(y0.x, y0.y));
