@@ -301,7 +301,9 @@ __device__ inline void rhs_entries(const SubDesc& sd, int k, int bwd, int qx, in
 }
 
 // FP32: sixteen lanes per plane row, two columns each (whole cache lines per
-// load, one coefficient broadcast per row), one 16-byte store per lane.
+// load), one 16-byte store per lane.  The nine couplings of the block's rows
+// to the neighbouring plane are staged in LDS once, not loaded by every lane
+// of a row.
 constexpr int RB_ROWS = 16;
 __global__ void __launch_bounds__(RB_ROWS * 16)
 blr_rhs_f32_kernel(const SubDesc* __restrict__ subs, const BlrSub* __restrict__ bsubs,
@@ -309,15 +311,60 @@ blr_rhs_f32_kernel(const SubDesc* __restrict__ subs, const BlrSub* __restrict__ 
                    const float2* __restrict__ lca, const float2* __restrict__ ybuf,
                    float2* __restrict__ bt, const double2* __restrict__ v,
                    const double* __restrict__ scale, int nx, int ny, int s, int s16) {
+  __shared__ float2 cpl[9][RB_ROWS];
   const SubDesc sd = subs[blockIdx.y];
   if (!plane_active(sd, k, bwd)) return;
   const int rb = blockIdx.x % nrb, cc = blockIdx.x / nrb;
-  const int q = rb * RB_ROWS + (threadIdx.x >> 4);
+  const bool couple = bwd || k > 0;
+  if (couple) {
+    const long long nbox = (long long)sd.sx * sd.sy * sd.sz;
+    const int ez = bwd ? 1 : -1;
+    const float sg = bwd ? 1.f : -1.f;
+    for (int i = threadIdx.x; i < 9 * RB_ROWS; i += RB_ROWS * 16) {
+      const int e = i / RB_ROWS, r = i % RB_ROWS, qq = rb * RB_ROWS + r;
+      float2 l = make_float2(0.f, 0.f);
+      if (qq < sd.p) {
+        const long long node = ((long long)k * sd.sy + qq / sd.sx) * sd.sx + qq % sd.sx;
+        l = lca[sd.lca_off + eidx(e % 3 - 1, e / 3 - 1, ez) * nbox + node];
+        l.x *= sg;
+        l.y *= sg;
+      }
+      cpl[e][r] = l;
+    }
+    __syncthreads();
+  }
+  const int rl = threadIdx.x >> 4;
+  const int q = rb * RB_ROWS + rl;
   const int c = 32 * cc + 2 * (threadIdx.x & 15);
   if (q >= sd.p || c >= s) return;                 // s is even
   const int qx = q % sd.sx, qy = q / sd.sx;
   float2 t[2];
-  rhs_entries<float, 2>(sd, k, bwd, qx, qy, c, lca, ybuf, v, scale, nx, ny, s, t);
+#pragma unroll
+  for (int j = 0; j < 2; ++j) t[j] = make_float2(0.f, 0.f);
+  if (!bwd) {
+    const long long g = ((long long)(sd.lo[2] + k) * ny + sd.lo[1] + qy) * nx + sd.lo[0] + qx;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const double2 vv = v[g * s + c + j];
+      const double sc = scale ? scale[c + j] : 1.0;
+      t[j] = make_float2((float)(vv.x * sc), (float)(vv.y * sc));
+    }
+  }
+  if (couple) {
+    const float2* Yn = ybuf + (sd.y_off + (long long)(bwd ? k + 1 : k - 1) * sd.P) * s + c;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int py = min(max(qy + dy, 0), sd.sy - 1);
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int px = min(max(qx + dx, 0), sd.sx - 1);
+        const float2 l = cpl[(dy + 1) * 3 + dx + 1][rl];
+        const float4 yr = *reinterpret_cast<const float4*>(Yn + (long long)(py * sd.sx + px) * s);
+        cfma(t[0], l, make_float2(yr.x, yr.y));
+        cfma(t[1], l, make_float2(yr.z, yr.w));
+      }
+    }
+  }
   const BlrSub bs = bsubs[blockIdx.y];
   *reinterpret_cast<float4*>(bt + (bs.bt_off + t_row(sd, bs, lists, qx, qy)) * s16 + c) =
       make_float4(t[0].x, t[0].y, t[1].x, t[1].y);

@@ -63,56 +63,17 @@ __device__ inline bool plane_active(const SubDesc& sd, int k, int bwd) {
   return bwd ? (k <= sd.sz - 2 && k >= sd.olo[2] - sd.lo[2]) : (k < sd.sz);
 }
 
-// Right-hand side of one plane row q, column c (q < p, c < s):
-// forward scale * v - L_k y_{k-1} (the L part only for k > 0), backward U_k x_{k+1}.
-template <typename R>
-__device__ inline C<R> plane_rhs_entry(const SubDesc& sd, int k, int bwd, int q, int c,
-                                       const C<R>* __restrict__ lca, const C<R>* __restrict__ ybuf,
-                                       const double2* __restrict__ v,
-                                       const double* __restrict__ scale, int nx, int ny, int s) {
-  using T = C<R>;
-  T t;
-  t.x = 0;
-  t.y = 0;
-  const int qx = q % sd.sx, qy = q / sd.sx;
-  if (!bwd) {
-    const long long g = ((long long)(sd.lo[2] + k) * ny + sd.lo[1] + qy) * nx + sd.lo[0] + qx;
-    const double2 vv = v[g * s + c];
-    const double sc = scale ? scale[c] : 1.0;
-    t.x = (R)(vv.x * sc);
-    t.y = (R)(vv.y * sc);
-  }
-  if (bwd || k > 0) {
-    const long long nbox = (long long)sd.sx * sd.sy * sd.sz;
-    const long long node = ((long long)k * sd.sy + qy) * sd.sx + qx;
-    const T* L = lca + sd.lca_off;
-    const T* Yn = ybuf + (sd.y_off + (long long)(bwd ? k + 1 : k - 1) * sd.P) * s;
-    const int ez = bwd ? 1 : -1;
-    // couplings that leave the box are stored as exact zeros in the local
-    // coefficients (the restricted rows drop them), so clamped neighbour
-    // indices contribute nothing and the loads need no branches
-#pragma unroll
-    for (int dy = -1; dy <= 1; ++dy) {
-      const int py = min(max(qy + dy, 0), sd.sy - 1);
-#pragma unroll
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int px = min(max(qx + dx, 0), sd.sx - 1);
-        const T l = L[eidx(dx, dy, ez) * nbox + node];
-        const T y = Yn[(long long)(py * sd.sx + px) * s + c];
-        if (bwd) cfma(t, l, y);
-        else cfms(t, l, y);
-      }
-    }
-  }
-  return t;
-}
-
-// The right-hand-side kernel of the complex FP32 path forms t for 32 plane
-// rows and 32 columns per work-group: eight lanes share a row, four columns
-// each, so every vector load of y or v covers whole cache lines of one row
-// and a coupling coefficient is one broadcast per row, loaded once per four
-// columns (with sixteen lanes of two columns: 63.2 against 61.9 us per plane
-// step on 160^3, 32 RHS).
+// The plane right-hand side: forward scale * v - L_k y_{k-1} (the L part only
+// for k > 0), backward U_k x_{k+1}.  Couplings that leave the box are stored
+// as exact zeros in the local coefficients (the restricted rows drop them),
+// so clamped neighbour indices contribute nothing and the loads need no
+// branches.
+//
+// The kernel of the complex FP32 path forms t for 32 plane rows and 32
+// columns per work-group: eight lanes share a row, four columns each, so
+// every vector load of y or v covers whole cache lines of one row; the
+// block's couplings are staged in LDS once (with sixteen lanes of two
+// columns: 63.2 against 61.9 us per plane step on 160^3, 32 RHS).
 constexpr int RB_ROWS = 32;
 constexpr int RB_THREADS = RB_ROWS * 8;
 
@@ -395,18 +356,67 @@ plane_gemm_x3_kernel(const SubDesc* __restrict__ subs, int nsub, int max_ng, int
 // Both 16x16x4 FP64 operands: A[row = lane % 16][k = lane / 16],
 // B[k = lane / 16][col = lane % 16]; result item t of lane l is row l / 16 + 4 t,
 // column l % 16 (checked on gfx950).
-__global__ void plane_rhs_f64_kernel(const SubDesc* __restrict__ subs, int k, int bwd,
+
+// The FP64 right-hand side, one thread per entry; the rows a 256-thread
+// block touches (256 entries, s >= 8 of them per row, the first row possibly
+// partial) have their couplings staged in LDS once.
+constexpr int RHS64_ROWS = 256 / 8 + 1;
+__global__ void __launch_bounds__(256)
+plane_rhs_f64_kernel(const SubDesc* __restrict__ subs, int k, int bwd,
                                      const double2* __restrict__ lca,
                                      const double2* __restrict__ ybuf, double2* __restrict__ tvbuf,
                                      const double2* __restrict__ v,
                                      const double* __restrict__ scale, int nx, int ny, int s) {
+  // the couplings of the block's rows (at most 256 / 8 + 1 of them) are
+  // staged in LDS once, not loaded for every right-hand side
+  __shared__ double2 cpl[9][RHS64_ROWS];
   const SubDesc sd = subs[blockIdx.y];
   if (!plane_active(sd, k, bwd)) return;
-  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long idx0 = (long long)blockIdx.x * blockDim.x;
+  const long long idx = idx0 + threadIdx.x;
+  const int qf = (int)(idx0 / s);
+  const bool couple = bwd || k > 0;
+  if (couple) {
+    const long long nbox = (long long)sd.sx * sd.sy * sd.sz;
+    const int ez = bwd ? 1 : -1;
+    const double sg = bwd ? 1.0 : -1.0;
+    for (int i = threadIdx.x; i < 9 * RHS64_ROWS; i += blockDim.x) {
+      const int e = i / RHS64_ROWS, r = i % RHS64_ROWS, qq = qf + r;
+      double2 l = make_double2(0.0, 0.0);
+      if (qq < sd.p) {
+        const long long node = ((long long)k * sd.sy + qq / sd.sx) * sd.sx + qq % sd.sx;
+        l = lca[sd.lca_off + eidx(e % 3 - 1, e / 3 - 1, ez) * nbox + node];
+        l.x *= sg;
+        l.y *= sg;
+      }
+      cpl[e][r] = l;
+    }
+    __syncthreads();
+  }
   if (idx >= (long long)sd.P * s) return;
   const int q = (int)(idx / s), c = (int)(idx % s);
   double2 t = make_double2(0.0, 0.0);
-  if (q < sd.p) t = plane_rhs_entry<double>(sd, k, bwd, q, c, lca, ybuf, v, scale, nx, ny, s);
+  if (q < sd.p) {
+    const int qx = q % sd.sx, qy = q / sd.sx;
+    if (!bwd) {
+      const long long g = ((long long)(sd.lo[2] + k) * ny + sd.lo[1] + qy) * nx + sd.lo[0] + qx;
+      const double2 vv = v[g * s + c];
+      const double sc = scale ? scale[c] : 1.0;
+      t = make_double2(vv.x * sc, vv.y * sc);
+    }
+    if (couple) {
+      const double2* Yn = ybuf + (sd.y_off + (long long)(bwd ? k + 1 : k - 1) * sd.P) * s + c;
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy) {
+        const int py = min(max(qy + dy, 0), sd.sy - 1);
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int px = min(max(qx + dx, 0), sd.sx - 1);
+          cfma(t, cpl[(dy + 1) * 3 + dx + 1][q - qf], Yn[(long long)(py * sd.sx + px) * s]);
+        }
+      }
+    }
+  }
   tvbuf[sd.tv_off * (long long)pad16(s) + idx] = t;
 }
 
