@@ -47,11 +47,14 @@ template <> struct Tiny<float> { static constexpr float v = 1e-30f; };
 template <> struct Tiny<double> { static constexpr double v = 1e-280; };
 
 // T = S_{k-1}^{-1} U_{k-1}:  T[a, c] = sum_d Sinv[a, c - d] U[c - d, c], where
-// U[c', c] couples node c' of plane k-1 to node c of plane k.
+// U[c', c] couples node c' of plane k-1 to node c of plane k.  The couplings
+// of the tile's 32 columns are staged in LDS once (every row of the tile uses
+// them).
 template <typename R>
 __global__ void __launch_bounds__(256) schur_T_kernel(const SubDesc* subs, int k, const C<R>* fac,
                                                       C<R>* tbuf, const C<R>* lca) {
   using T = C<R>;
+  __shared__ T ucol[9][TILE];
   const SubDesc sd = subs[blockIdx.z];
   if (k == 0 || k >= sd.sz) return;
   const int nt = sd.nt;
@@ -62,6 +65,19 @@ __global__ void __launch_bounds__(256) schur_T_kernel(const SubDesc* subs, int k
   T* Tm = tbuf + sd.t_off;
   const long long nbox = (long long)sd.sx * sd.sy * sd.sz;
   const T* L = lca + sd.lca_off;
+  for (int i = threadIdx.x; i < 9 * TILE; i += 256) {
+    // coupling of column c to its neighbour (c - d) in plane k - 1, d = (dx, dy)
+    const int d = i / TILE, c = J * TILE + i % TILE;
+    const int dx = d % 3 - 1, dy = d / 3 - 1;
+    T u = czero<T>();
+    if (c < sd.p) {
+      const int px = c % sd.sx - dx, py = c / sd.sx - dy;
+      if (px >= 0 && px < sd.sx && py >= 0 && py < sd.sy)
+        u = L[eidx(dx, dy, 1) * nbox + ((long long)(k - 1) * sd.sy + py) * sd.sx + px];
+    }
+    ucol[d][i % TILE] = u;
+  }
+  __syncthreads();
   for (int q = 0; q < 4; ++q) {
     const int e = threadIdx.x + 256 * q;
     const int c4 = e >> 7, r = (e >> 2) & 31, cl = e & 3;
@@ -75,10 +91,8 @@ __global__ void __launch_bounds__(256) schur_T_kernel(const SubDesc* subs, int k
         for (int dx = -1; dx <= 1; ++dx) {
           const int px = cx - dx;
           if (px < 0 || px >= sd.sx) continue;
-          const long long node = ((long long)(k - 1) * sd.sy + py) * sd.sx + px;
-          const T u = L[eidx(dx, dy, 1) * nbox + node];
           const T s = Sinv[mat_off(a, py * sd.sx + px, nt)];
-          cfma(acc, s, u);
+          cfma(acc, s, ucol[(dy + 1) * 3 + dx + 1][c4 * 4 + cl]);
         }
       }
     }
@@ -89,12 +103,15 @@ __global__ void __launch_bounds__(256) schur_T_kernel(const SubDesc* subs, int k
 // S_k = D_k - L_k T  (just D_k on the first plane), identity on the pad.
 // stats[2 (sub max_sz + k)] receives the bits of max |S_k|^2 (a non-negative
 // double, so its bits order as the value).
+// The couplings of the tile's 32 rows to plane k - 1 are staged in LDS once
+// (every column of the tile uses them).
 template <typename R>
 __global__ void __launch_bounds__(256) build_S_kernel(const SubDesc* subs, int k, C<R>* fac,
                                                       const C<R>* tbuf, const C<R>* lca,
                                                       unsigned long long* stats, int max_sz) {
   using T = C<R>;
   __shared__ double red[256];
+  __shared__ T lrow[9][TILE];
   const SubDesc sd = subs[blockIdx.z];
   if (k >= sd.sz) return;
   const int nt = sd.nt;
@@ -106,6 +123,17 @@ __global__ void __launch_bounds__(256) build_S_kernel(const SubDesc* subs, int k
   const T* Tm = tbuf + sd.t_off;
   const long long nbox = (long long)sd.sx * sd.sy * sd.sz;
   const T* L = lca + sd.lca_off;
+  if (k > 0) {
+    for (int i = threadIdx.x; i < 9 * TILE; i += 256) {
+      const int e = i / TILE, b = I * TILE + i % TILE;
+      T l = czero<T>();
+      if (b < sd.p)
+        l = L[eidx(e % 3 - 1, e / 3 - 1, -1) * nbox +
+              ((long long)k * sd.sy + b / sd.sx) * sd.sx + b % sd.sx];
+      lrow[e][i % TILE] = l;
+    }
+    __syncthreads();
+  }
   for (int q = 0; q < 4; ++q) {
     const int e = threadIdx.x + 256 * q;
     const int c4 = e >> 7, r = (e >> 2) & 31, cl = e & 3;
@@ -126,9 +154,8 @@ __global__ void __launch_bounds__(256) build_S_kernel(const SubDesc* subs, int k
           for (int ex = -1; ex <= 1; ++ex) {
             const int qx = bx + ex;
             if (qx < 0 || qx >= sd.sx) continue;
-            const T l = L[eidx(ex, ey, -1) * nbox + node];
             const T t = Tm[mat_off(qy * sd.sx + qx, c, nt)];
-            cfms(v, l, t);
+            cfms(v, lrow[(ey + 1) * 3 + ex + 1][r], t);
           }
         }
       }

@@ -29,6 +29,7 @@ CASES = [
     dict(n=(37, 20, 19), npml=2, q=None, nrhs=13, seed=32),   # ragged tiles, 2 chunks
     dict(n=(21, 18, 11), npml=0, q=50.0, nrhs=40, seed=33),   # no PML: interior tiles only
     dict(n=(33, 17, 21), npml=2, q=70.0, nrhs=50, seed=37),   # chunks of 32, 16 and 8 RHS
+    dict(n=(18, 17, 9), npml=2, q=None, nrhs=256, seed=38),   # the widest block
 ]
 
 
