@@ -57,6 +57,10 @@ struct DevBuf {
 struct oras_ctx_s {
   int device = -1;
   hipStream_t stream = nullptr;
+  // a second stream (and its fork/join events) for the factorisation, which
+  // runs the two halves of the subdomains side by side
+  hipStream_t stream2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool host_only = true;
   std::string err;
 
@@ -118,6 +122,9 @@ struct oras_ctx_s {
   ~oras_ctx_s() {
     release_all();
     for (hipEvent_t e : gemm_ev) (void)hipEventDestroy(e);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (stream2) (void)hipStreamDestroy(stream2);
   }
   void release_blr() {
     blr_bsubs.release(); blr_items.release(); blr_lists.release(); blr_store.release();
@@ -868,22 +875,44 @@ oras_status oras_factor_subdomains_ex(oras_ctx c, const int parts[3], int overla
   launch_assemble_local(opview(c), c->subs_dev.as<SubDesc>(), (int)subs.size(), max_box, c->lca.p,
                         factor_prec, ifc, c->stream);
   HIP_TRY(c, hipGetLastError());
-  for (int k = 0; k < max_sz; ++k) {
-    if (factor_prec == ORAS_C64)
-      launch_factor_plane<float>(c->subs_dev.as<SubDesc>(), (int)subs.size(), k, max_nt, max_sz,
-                                 c->fac.as<float2>(), tbuf.as<float2>(), c->lca.as<float2>(),
-                                 c->status.as<int>(), c->pstat.as<unsigned long long>(),
-                                 c->stream);
-    else
-      launch_factor_plane<double>(c->subs_dev.as<SubDesc>(), (int)subs.size(), k, max_nt, max_sz,
-                                  c->fac.as<double2>(), tbuf.as<double2>(), c->lca.as<double2>(),
-                                  c->status.as<int>(), c->pstat.as<unsigned long long>(),
-                                  c->stream);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) {
-      c->release_factors();
-      return fail(c, ORAS_E_HIP, std::string("factor launch: ") + hipGetErrorString(e));
+  // The subdomains are independent: two halves run their plane recursions on
+  // two streams, so that one half's latency-bound kernels (the diagonal-block
+  // inversions) overlap the other half's products.
+  const int nsub = (int)subs.size();
+  const int nh = nsub >= 16 ? nsub / 16 * 8 : nsub;
+  const int nparts = nh < nsub ? 2 : 1;
+  if (nparts == 2) {
+    if (!c->stream2) {
+      HIP_TRY(c, hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking));
+      HIP_TRY(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+      HIP_TRY(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
     }
+    HIP_TRY(c, hipEventRecord(c->ev_fork, c->stream));
+    HIP_TRY(c, hipStreamWaitEvent(c->stream2, c->ev_fork, 0));
+  }
+  for (int part = 0; part < nparts; ++part) {
+    const int s0 = part == 0 ? 0 : nh, ns = part == 0 ? nh : nsub - nh;
+    hipStream_t st = part == 0 ? c->stream : c->stream2;
+    const SubDesc* sd = c->subs_dev.as<SubDesc>() + s0;
+    int* status = c->status.as<int>() + s0;
+    unsigned long long* pstat = c->pstat.as<unsigned long long>() + 2 * (size_t)s0 * max_sz;
+    for (int k = 0; k < max_sz; ++k) {
+      if (factor_prec == ORAS_C64)
+        launch_factor_plane<float>(sd, ns, k, max_nt, max_sz, c->fac.as<float2>(),
+                                   tbuf.as<float2>(), c->lca.as<float2>(), status, pstat, st);
+      else
+        launch_factor_plane<double>(sd, ns, k, max_nt, max_sz, c->fac.as<double2>(),
+                                    tbuf.as<double2>(), c->lca.as<double2>(), status, pstat, st);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) {
+        c->release_factors();
+        return fail(c, ORAS_E_HIP, std::string("factor launch: ") + hipGetErrorString(e));
+      }
+    }
+  }
+  if (nparts == 2) {
+    HIP_TRY(c, hipEventRecord(c->ev_join, c->stream2));
+    HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
   }
   std::vector<int> stat(subs.size(), 0);
   std::vector<unsigned long long> pst(nstat, 0);
