@@ -57,18 +57,22 @@ namespace oras {
 namespace {
 
 // Tiles of TX x TY x TZ nodes (measured on a 160^3 grid with 32 right-hand
-// sides: marching 32 planes, or PML tiles of 16 x 4, was no faster per node)
-constexpr int TX = 16;
+// sides: 8 x 8 columns beat 16 x 8 and 16 x 4 by 2-6 %; marching 32 planes
+// was no faster per node)
+constexpr int TX = 8;
 constexpr int TY = 8;
 constexpr int TZ = 16;
 constexpr int NXCD = 8;
 constexpr int NS = 4;                  // lanes per node: one DPP quad
 constexpr int NTHREADS = TX * TY * NS;
 
-// widest chunk of right-hand sides per work-group (256 bytes per node)
-template <typename R> struct MfChunk;
-template <> struct MfChunk<float> { static constexpr int RC = 32; };
-template <> struct MfChunk<double> { static constexpr int RC = 16; };
+// widest chunk of right-hand sides per work-group.  PML tiles take 256 bytes
+// per node (their couplings cost more arithmetic, formed once per chunk);
+// PML-free tiles in single precision take 16 right-hand sides, which leaves
+// room for two work-groups per CU.
+template <typename R, bool PML> struct MfChunk;
+template <bool PML> struct MfChunk<float, PML> { static constexpr int RC = PML ? 32 : 16; };
+template <bool PML> struct MfChunk<double, PML> { static constexpr int RC = 16; };
 
 template <typename R> __device__ inline C<R> cz() { C<R> z; z.x = 0; z.y = 0; return z; }
 template <typename R> __device__ inline C<R> csc(C<R> a, R s) { a.x *= s; a.y *= s; return a; }
@@ -403,7 +407,7 @@ void launch_kind(const StencilMF<R>& op, const C<R>* x, const double2* b, double
                  int ny, int nz, int s, hipStream_t st) {
   // chunks of the widest width, then narrower chunks for the rest (s is a
   // multiple of 8)
-  constexpr int RC = MfChunk<R>::RC;
+  constexpr int RC = MfChunk<R, PML>::RC;
   const int full = s / RC;
   int c = full * RC;
   launch_chunks<R, PML, RC>(op, x, b, y, nx, ny, nz, s, 0, full, st);

@@ -3,9 +3,12 @@ element by element (paper sec. 2.3, FDFD stencil).
 
 The apply forms each row's coefficients from node fields and the 1D PML
 profiles inside the kernel, with a reduced form on tiles the PML does not
-reach.  The grids below are sized so that both kinds of tile run (16 x 16 x 8
-tiles: with npml = 3 the nodes 4 .. n - 5 use only unit profile values), with
-ragged tiles on every axis, and one grid has no PML at all.  The bar is per
+reach.  The grids below are sized so that both kinds of tile run in one apply (8 x 8
+x 16 tiles: with npml = 3 the nodes 4 .. n - 5 use only unit profile values,
+so the first grid has PML-free tiles at planes 16 .. 31), with ragged tiles
+on every axis, and one grid has no PML at all.  The chunk widths differ by
+kind (32 right-hand sides on PML tiles, 16 elsewhere in single precision), so
+the right-hand-side counts cover full and partial chunks of both.  The bar is per
 entry, relative to sum_e |c_e| |x_e| of that row (the size of the terms the
 entry sums), so a wrong coupling in one row or one tile fails on its own.
 """
@@ -25,7 +28,7 @@ FP64_ROW = 1e-12
 FP32_ROW = 32 * EPS32
 
 CASES = [
-    dict(n=(40, 36, 26), npml=3, q=80.0, nrhs=1, seed=31),    # PML and interior tiles
+    dict(n=(40, 36, 38), npml=3, q=80.0, nrhs=1, seed=31),    # PML and interior tiles
     dict(n=(37, 20, 19), npml=2, q=None, nrhs=13, seed=32),   # ragged tiles, 2 chunks
     dict(n=(21, 18, 11), npml=0, q=50.0, nrhs=40, seed=33),   # no PML: interior tiles only
     dict(n=(33, 17, 21), npml=2, q=70.0, nrhs=50, seed=37),   # chunks of 32, 16 and 8 RHS
