@@ -216,7 +216,7 @@ gj_diag_kernel(const SubDesc* subs, int k, int kb0, C<R>* fac, int* status,
       for (int j = 0; j < 4; ++j) a[i][j] = blk[in_tile((r0 + i) % TILE, (c0 % TILE) + j)];
   }
   if (threadIdx.x == 0) bad = 0;
-  double inv_min = 0.0;    // largest 1 / |pivot|^2 seen (thread 0)
+  R mag_min = INFINITY;    // smallest |pivot|^2 seen (thread 0)
   for (int piv = 0; piv < nr; ++piv) {
     const int pi = piv - r0, pj = piv - c0;
     if (live) {
@@ -237,35 +237,44 @@ gj_diag_kernel(const SubDesc* subs, int k, int kb0, C<R>* fac, int* status,
     const T p = rowb[piv];
     const R mag = p.x * p.x + p.y * p.y;
     const bool ok = isfinite(p.x) && isfinite(p.y) && mag > Tiny<R>::v;
+    const R inv = (R)1 / (ok ? mag : (R)1);
     T ip;
-    {
-      const R d = ok ? mag : (R)1;
-      ip.x = p.x / d;
-      ip.y = -p.y / d;
-    }
+    ip.x = p.x * inv;
+    ip.y = -p.y * inv;
     if (!ok && threadIdx.x == 0) bad = 1;
-    if (ok && threadIdx.x == 0 && piv < sd.p - TILE * kb0) inv_min = fmax(inv_min, 1.0 / (double)mag);
+    if (ok && threadIdx.x == 0 && piv < sd.p - TILE * kb0) mag_min = fmin(mag_min, mag);
     if (live) {
+      // every entry as if off the pivot row and column (straight-line code),
+      // then the pivot row and column rewritten from the published copies
+      T rv[4], f[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int r = r0 + i;
-        const T f = cmul(colb[r], ip);          // A_r,piv / p
+      for (int j = 0; j < 4; ++j) rv[j] = rowb[c0 + j];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int c = c0 + j;
-          if (r == piv) {
-            a[i][j] = (c == piv) ? ip : cmul(a[i][j], ip);
-          } else if (c == piv) {
-            a[i][j].x = -f.x;
-            a[i][j].y = -f.y;
-          } else {
-            cfms(a[i][j], f, rowb[c]);
+      for (int i = 0; i < 4; ++i) f[i] = cmul(colb[r0 + i], ip);   // A_r,piv / p
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) cfms(a[i][j], f[i], rv[j]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (pi == i) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) a[i][j] = cmul(rv[j], ip);       // A_piv,c / p
+        }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (pj == j) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {                               // -A_r,piv / p
+            a[i][j].x = pi == i ? ip.x : -f[i].x;
+            a[i][j].y = pi == i ? ip.y : -f[i].y;
           }
         }
-      }
     }
     __syncthreads();
   }
+  // largest 1 / |pivot|^2 over the block's pivots
+  const double inv_min = mag_min < INFINITY ? 1.0 / (double)mag_min : 0.0;
   if (live) {
 #pragma unroll
     for (int i = 0; i < 4; ++i)
