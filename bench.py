@@ -103,7 +103,7 @@ def traffic_for(workload: str, summary: str = "plane_gemm_traffic.json",
     return entry.get("bytes_per_launch")
 
 
-def cpu_baseline(w, nrhs, iters, replica_n=40, k=3):
+def cpu_baseline(w, nrhs, iters, replica_n=40, k=25):
     """The oracle's own ORAS-FGMRES, end to end, on a replica of the workload.
 
     Sample: the config-5 generator at replica_n^3 (same h, PML, frequency,
