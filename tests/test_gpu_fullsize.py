@@ -3,7 +3,9 @@
 The oracle cannot solve these sizes, so it checks sampled outputs and
 properties that hold at any size:
   * the 27 coefficients of sampled rows (windows in the PML, the interior and
-    a corner) against the oracle's assembly;
+    a corner) against the oracle's assembly, and the single-precision
+    matrix-free apply on those rows (the workload's RHS count) against the
+    oracle's coefficients applied to the same x;
   * the true residual of the GPU solution meets tol, and so does the oracle's
     own whole-grid residual b - A x (its coefficients of every row) for two
     columns, which equals the GPU residual entry by entry;
@@ -26,7 +28,10 @@ import torch
 from oracle import blr as oblr, direct, operator as op, oras as ooras
 from paper_2110_15113_amd import workloads as wl
 
-from gpu_util import FP32_BOX, FP64_BOX, need_gpu, say
+from gpu_util import EPS32, FP32_BOX, FP64_BOX, need_gpu, say
+
+# single-precision stencil rows: a few roundings per term, 27 terms
+FP32_ROW = 32 * EPS32
 
 pytestmark = pytest.mark.gpu
 
@@ -58,6 +63,42 @@ def _check_coefficients(S, F, w):
         got = C[:, lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]].cpu().numpy()
         assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max(), lo
     del C
+
+
+def _check_fp32_apply(S, F, w, nrhs):
+    """The single-precision matrix-free apply of the Krylov loop, in the
+    launch configuration the benchmark times (the workload's grid and RHS
+    count), against the oracle's coefficients of the rows of three windows
+    (a PML corner, the interior, a PML face) applied to the same x, entry
+    by entry relative to sum_e |c_e| |x_e| of the row."""
+    g = torch.Generator(device=S.device)
+    g.manual_seed(7)
+    x = torch.randn((nrhs, w.nz, w.ny, w.nx), dtype=torch.complex128, device=S.device,
+                    generator=g)
+    y = S.apply_A(x, prec=1)
+    n = (w.nx, w.ny, w.nz)
+    worst = 0.0
+    for lo in _windows(w):
+        hi = tuple(min(l + 5, m) for l, m in zip(lo, n))
+        C = op.row_coeffs(F, lo, hi)
+        wz, wy, wx = C.shape[1:]
+        # x over the window and one layer around it (zero outside the grid)
+        xp = np.zeros((nrhs, wz + 2, wy + 2, wx + 2), dtype=np.complex128)
+        a = [max(l - 1, 0) for l in lo]
+        e = [min(h + 1, m) for h, m in zip(hi, n)]
+        xp[:, a[2] - lo[2] + 1:e[2] - lo[2] + 1, a[1] - lo[1] + 1:e[1] - lo[1] + 1,
+           a[0] - lo[0] + 1:e[0] - lo[0] + 1] = x[:, a[2]:e[2], a[1]:e[1], a[0]:e[0]].cpu().numpy()
+        ref = np.zeros((nrhs, wz, wy, wx), dtype=np.complex128)
+        scale = np.zeros((nrhs, wz, wy, wx))
+        for ei, (ex, ey, ez) in enumerate(op.OFFSETS):
+            xs = xp[:, 1 + ez:wz + 1 + ez, 1 + ey:wy + 1 + ey, 1 + ex:wx + 1 + ex]
+            ref += C[ei] * xs
+            scale += np.abs(C[ei]) * np.abs(xs)
+        got = y[:, lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]].cpu().numpy()
+        worst = max(worst, float((np.abs(got - ref) / scale).max()))
+    say(f"  FP32 matrix-free apply, {nrhs} RHS: worst row error {worst:.2e}")
+    assert worst < FP32_ROW, worst
+    del x, y
 
 
 def _check_residual(S, F, w, b, x, tol, C):
@@ -154,6 +195,7 @@ def test_mixed_workload_against_fp64(cfg):
     say(f"full-size mixed config {cfg}")
     F = op.make_fields(w.vel, w.Q, w.omega, w.h, w.npml)
     S = _solver(w, oras.C64)
+    _check_fp32_apply(S, F, w, len(w.sources))
     _check_local_solve(S, F, w, FP32_BOX)
     b = S.point_sources(w.sources)
     rm = S.solve(b, w.tol, restart=w.restart, maxit=w.maxit)
