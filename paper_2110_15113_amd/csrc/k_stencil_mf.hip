@@ -31,8 +31,9 @@
 // mu_ij = omega^2 (wm_t,i + wm_t,j)/2 (m~_i + m~_j)/2 (S_i + S_j)/2.
 //
 // Tiling.  A work-group owns a TX x TY tile and a chunk of RC right-hand
-// sides (all of them, up to 32 in single precision) and streams the planes
-// p = k0 - 1 .. k0 + TZ through LDS one at a time: each x value of plane p is
+// sides (up to 32 on PML tiles, 16 elsewhere in single precision) and
+// streams the planes p = k0 - 1 .. k0 + TZ through LDS one at a time: each
+// x value of plane p is
 // read once from LDS and applied to the three outputs it couples to (planes
 // p - 1, p and p + 1 of the same column), which the threads keep in registers
 // and write once complete.  Four lanes (a DPP quad) share a node, RC / 4
