@@ -33,10 +33,9 @@
 // Tiling.  A work-group owns a TX x TY tile and a chunk of RC right-hand
 // sides (up to 32 on PML tiles, 16 elsewhere in single precision) and
 // streams the planes p = k0 - 1 .. k0 + TZ through LDS one at a time: each
-// x value of plane p is
-// read once from LDS and applied to the three outputs it couples to (planes
-// p - 1, p and p + 1 of the same column), which the threads keep in registers
-// and write once complete.  Four lanes (a DPP quad) share a node, RC / 4
+// x value of plane p is read once from LDS and applied to the three outputs
+// it couples to (planes p - 1, p and p + 1 of the same column), which the
+// threads keep in registers and write once complete.  Four lanes (a DPP quad) share a node, RC / 4
 // right-hand sides each: for every neighbour column, lane o forms the
 // coupling of output plane p - 1 + o (lane 3 idles) and the quad exchanges
 // the three couplings by DPP broadcasts, so a coupling is formed once per
