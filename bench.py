@@ -479,7 +479,8 @@ def main():
                  "three-piece operand splits, local substitutions)" if P == oras.C64
                  else "plane_gemm_f64_kernel (MFMA 16x16x4 f64, local substitutions)")
         if args.blr is not None:
-            kname = ("blr_gemm_f32_kernel projection + expansion (MFMA 32x32x2 f32, BLR local "
+            kname = ("blr_gemm_x3_kernel projection + expansion (complex FP32 products on MFMA "
+                     "32x32x16 bf16 with exact three-piece operand splits, BLR local "
                      "substitutions)" if P == oras.C64 else
                      "blr_gemm_f64_kernel projection + expansion (MFMA 16x16x4 f64, BLR local "
                      "substitutions)")

@@ -399,21 +399,24 @@ __device__ inline bool item_map(int nitems, int ncg, int& it, int& cg) {
   return it < nitems;
 }
 
-// Complex FP32: 32x32x2 MFMA, RT tiles of 32 rows x 32 columns per wave.
-// Expansion items take 32 rows in both precisions (a row patch of more than
-// 32 nodes is two items, the second from row0 = 32): with one tile the wave
-// needs 132 registers and three share a SIMD, where two tiles took 224 and
-// two waves (117 against 129 us per plane step on 160^3, 32 RHS).
-// Operand row kk of the item is operand-buffer row rbase + (kk - 4 kq) for the
-// 4-row group kq; projection items read the patch's t rows, expansion items
-// walk their segments.
-template <int RT, int MODE, typename Z>
+// Complex FP32 on the bf16 instruction (32x32x16) with exactly split operands,
+// as the dense plane products: every FP32 value of both operands is split
+// into three bf16 pieces and six piece products form each real product, so
+// each product carries an FP32-level error and accumulates in FP32.  One
+// wave takes 32 rows and one 32-column chunk; the real and imaginary parts
+// are separate accumulators.  A 16-k step covers four 4-row groups of the
+// stored operand: lane (n = lane % 32, g = lane / 32) holds the operand
+// entries (row n, k = 4 q + 2 g + e) and the t or T values (k = 4 q + 2 g + e,
+// column n), value i = 2 q + e of both instruction operands referring to the
+// same k.  A run of 4 m + 2 groups ends with a step whose last two groups are
+// zeroed in the stored operand.
+template <int MODE, typename Z>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
-blr_gemm_f32_kernel(const SubDesc* __restrict__ subs, const BlrSub* __restrict__ bsubs,
-                    const BlrItem* __restrict__ items, int nitems, int ncg, int k, int bwd,
-                    const float2* __restrict__ astore, const int* __restrict__ lists,
-                    float2* __restrict__ bt, float2* __restrict__ ybuf, Z* __restrict__ z,
-                    int nx, int ny, int s, int s16) {
+blr_gemm_x3_kernel(const SubDesc* __restrict__ subs, const BlrSub* __restrict__ bsubs,
+                   const BlrItem* __restrict__ items, int nitems, int ncg, int k, int bwd,
+                   const float2* __restrict__ astore, const int* __restrict__ lists,
+                   float2* __restrict__ bt, float2* __restrict__ ybuf, Z* __restrict__ z,
+                   int nx, int ny, int s, int s16) {
   using ZR = typename std::conditional<sizeof(Z) == 8, float, double>::type;
   int it, cg;
   if (!item_map(nitems, ncg, it, cg)) return;
@@ -422,82 +425,85 @@ blr_gemm_f32_kernel(const SubDesc* __restrict__ subs, const BlrSub* __restrict__
   const SubDesc sd = subs[item.sub];
   if (!plane_active(sd, k, bwd)) return;
   const BlrSub bs = bsubs[item.sub];
-  const float* btf = reinterpret_cast<const float*>(bt + bs.bt_off * s16);
+  const float2* btc = bt + bs.bt_off * s16;
   const float4* A = reinterpret_cast<const float4*>(astore + item.a_off);
-  const int lane = threadIdx.x, rr = lane & 31, h = lane >> 5;
-  const bool odd = (rr & 1) != 0;
-  const int c0 = 32 * cg;
+  const int lane = threadIdx.x, n = lane & 31, g = lane >> 5;
   // columns at or beyond s16 read column s16 - 1 (in bounds; their results are dropped)
-  int colf[2];
+  const int colb = min(32 * cg + n, s16 - 1);
+  f32x16 accR, accI;
 #pragma unroll
-  for (int nb = 0; nb < 2; ++nb) {
-    const int col = min(c0 + 16 * nb + (rr >> 1), s16 - 1);
-    colf[nb] = 2 * col + (rr & 1);
+  for (int j = 0; j < 16; ++j) {
+    accR[j] = 0.f;
+    accI[j] = 0.f;
   }
-  f32x16 acc[RT][2][2];
+  // groups kq .. kq + 3 of the run [q0, q1) whose group q0 starts at
+  // operand-buffer row rbase0; groups past the end repeat the last one with
+  // the stored operand zeroed
+  auto load = [&](int kq, int q0, int q1, int rbase0, float4 (&a)[4], float2 (&b)[8]) {
 #pragma unroll
-  for (int rt = 0; rt < RT; ++rt)
+    for (int q = 0; q < 4; ++q) {
+      const int gq = min(kq + q, q1 - 1);
+      a[q] = A[((long long)gq * item.mpad + item.row0 + n) * 2 + g];
+      if (kq + q >= q1) a[q] = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-    for (int nb = 0; nb < 2; ++nb)
-#pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        acc[rt][nb][0][j] = 0.f;
-        acc[rt][nb][1][j] = 0.f;
-      }
-  // one 4-row group: lane h takes operand rows 4 kq + 2 h + e, e = 0, 1
-  auto load = [&](int kq, int rbase, float (&bv)[2][2], float4 (&a)[RT]) {
-#pragma unroll
-    for (int e = 0; e < 2; ++e)
-#pragma unroll
-      for (int nb = 0; nb < 2; ++nb)
-        bv[e][nb] = btf[(long long)(rbase + 2 * h + e) * 2 * s16 + colf[nb]];
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-      a[rt] = A[((long long)kq * item.mpad + item.row0 + 32 * rt + rr) * 2 + h];
+      for (int e = 0; e < 2; ++e)
+        b[2 * q + e] = btc[(long long)(rbase0 + 4 * (gq - q0) + 2 * g + e) * s16 + colb];
+    }
   };
-  auto mma = [&](const float (&bv)[2][2], const float4 (&a)[RT]) {
+  auto mma = [&](const float4 (&a)[4], const float2 (&b)[8]) {
+    unsigned r1[4], r2[4], r3[4], i1[4], i2[4], i3[4];
+    unsigned s1[4], s2[4], s3[4], t1[4], t2[4], t3[4];
 #pragma unroll
-    for (int e = 0; e < 2; ++e)
-#pragma unroll
-      for (int nb = 0; nb < 2; ++nb) {
-        const float b1 = bv[e][nb];
-        const float sw = __int_as_float(__builtin_amdgcn_update_dpp(
-            __float_as_int(b1), __float_as_int(b1), 0xB1, 0xF, 0xF, false));
-        const float b2 = odd ? sw : -sw;
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt) {
-          const float ar = e ? a[rt].z : a[rt].x, ai = e ? a[rt].w : a[rt].y;
-          acc[rt][nb][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, b1, acc[rt][nb][0], 0, 0, 0);
-          acc[rt][nb][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, b2, acc[rt][nb][1], 0, 0, 0);
-        }
-      }
+    for (int q = 0; q < 4; ++q) {
+      split3(a[q].x, a[q].z, r1[q], r2[q], r3[q]);
+      split3(a[q].y, a[q].w, i1[q], i2[q], i3[q]);
+      split3(b[2 * q].x, b[2 * q + 1].x, s1[q], s2[q], s3[q]);
+      split3(b[2 * q].y, b[2 * q + 1].y, t1[q], t2[q], t3[q]);
+    }
+    const u32x4 sgn = {0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+    const bf16x8 Ar1 = as_bf16x8(u32x4{r1[0], r1[1], r1[2], r1[3]});
+    const bf16x8 Ar2 = as_bf16x8(u32x4{r2[0], r2[1], r2[2], r2[3]});
+    const bf16x8 Ar3 = as_bf16x8(u32x4{r3[0], r3[1], r3[2], r3[3]});
+    const bf16x8 Ai1 = as_bf16x8(u32x4{i1[0], i1[1], i1[2], i1[3]});
+    const bf16x8 Ai2 = as_bf16x8(u32x4{i2[0], i2[1], i2[2], i2[3]});
+    const bf16x8 Ai3 = as_bf16x8(u32x4{i3[0], i3[1], i3[2], i3[3]});
+    const bf16x8 Ni1 = as_bf16x8(u32x4{i1[0], i1[1], i1[2], i1[3]} ^ sgn);
+    const bf16x8 Ni2 = as_bf16x8(u32x4{i2[0], i2[1], i2[2], i2[3]} ^ sgn);
+    const bf16x8 Ni3 = as_bf16x8(u32x4{i3[0], i3[1], i3[2], i3[3]} ^ sgn);
+    const bf16x8 Br1 = as_bf16x8(u32x4{s1[0], s1[1], s1[2], s1[3]});
+    const bf16x8 Br2 = as_bf16x8(u32x4{s2[0], s2[1], s2[2], s2[3]});
+    const bf16x8 Br3 = as_bf16x8(u32x4{s3[0], s3[1], s3[2], s3[3]});
+    const bf16x8 Bi1 = as_bf16x8(u32x4{t1[0], t1[1], t1[2], t1[3]});
+    const bf16x8 Bi2 = as_bf16x8(u32x4{t2[0], t2[1], t2[2], t2[3]});
+    const bf16x8 Bi3 = as_bf16x8(u32x4{t3[0], t3[1], t3[2], t3[3]});
+#define ORAS_BX3(AR, AI, NI, BR, BI)                                           \
+  accR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(AR, BR, accR, 0, 0, 0);       \
+  accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(AR, BI, accI, 0, 0, 0);       \
+  accR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(NI, BI, accR, 0, 0, 0);       \
+  accI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(AI, BR, accI, 0, 0, 0);
+    ORAS_BX3(Ar1, Ai1, Ni1, Br1, Bi1)
+    ORAS_BX3(Ar1, Ai1, Ni1, Br2, Bi2)
+    ORAS_BX3(Ar2, Ai2, Ni2, Br1, Bi1)
+    ORAS_BX3(Ar1, Ai1, Ni1, Br3, Bi3)
+    ORAS_BX3(Ar3, Ai3, Ni3, Br1, Bi1)
+    ORAS_BX3(Ar2, Ai2, Ni2, Br2, Bi2)
+#undef ORAS_BX3
   };
-  // groups q0..q1-1 (a positive, even count: runs are whole multiples of 8
-  // rows) with operand rows from rbase0 on; two groups in flight in two
-  // register sets.  Nothing in the loop is conditional (loads past the end
-  // repeat the last group), so every path into it has the same loads
-  // outstanding and each multiply waits only for its own group.
+  // one run of groups [q0, q1): the next 16-k step is fetched while the
+  // current one feeds the products (loads past the end stay in bounds)
   auto run = [&](int q0, int q1, int rbase0) {
-    float b0[2][2], b1[2][2];
-    float4 a0[RT], a1[RT];
-    auto ld = [&](int kq, float (&bv)[2][2], float4 (&a)[RT]) {
-      const int g = min(kq, q1 - 1);
-      load(g, rbase0 + 4 * (g - q0), bv, a);
-    };
-    // the scheduling barriers keep each group's loads where they are issued
-    // (left to itself the scheduler sinks them to their first use)
-    ld(q0, b0, a0);
-    ld(q0 + 1, b1, a1);
-    __builtin_amdgcn_sched_barrier(0);
-    for (int kq = q0; kq < q1; kq += 2) {
-      mma(b0, a0);
-      __builtin_amdgcn_sched_barrier(0);
-      ld(kq + 2, b0, a0);
-      __builtin_amdgcn_sched_barrier(0);
-      mma(b1, a1);
-      __builtin_amdgcn_sched_barrier(0);
-      ld(kq + 3, b1, a1);
-      __builtin_amdgcn_sched_barrier(0);
+    float4 sa[4];
+    float2 sb[8];
+    load(q0, q0, q1, rbase0, sa, sb);
+    for (int kq = q0; kq < q1; kq += 4) {
+      float4 ca[4];
+      float2 cb[8];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) ca[q] = sa[q];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) cb[j] = sb[j];
+      load(kq + 4, q0, q1, rbase0, sa, sb);
+      mma(ca, cb);
     }
   };
   if (MODE == 0) {
@@ -508,83 +514,57 @@ blr_gemm_f32_kernel(const SubDesc* __restrict__ subs, const BlrSub* __restrict__
       run(seg.x >> 2, (seg.x + seg.z) >> 2, seg.y);
     }
   }
-  // accumulator item i of lane l: row 8 (i / 4) + 4 (l / 32) + i % 4, real column l % 32
+  // accumulator item i of lane l: row 8 (i / 4) + 4 (l / 32) + i % 4, column l % 32
+  const int col = 32 * cg + n;
   if (MODE == 0) {
     // destination rows first (all loads in flight together), then the stores
-    int dest[RT][16];
+    int dest[16];
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
+    for (int i = 0; i < 16; ++i) dest[i] = lists[item.list_off + 8 * (i / 4) + 4 * g + (i % 4)];
 #pragma unroll
-      for (int i = 0; i < 16; ++i)
-        dest[rt][i] = lists[item.list_off + 32 * rt + 8 * (i / 4) + 4 * h + (i % 4)];
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int lr = 32 * rt + 8 * (i / 4) + 4 * h + (i % 4);
-        if (lr >= item.rows) continue;
-        float* Tf = reinterpret_cast<float*>(bt + (bs.bt_off + dest[rt][i]) * s16);
-#pragma unroll
-        for (int nb = 0; nb < 2; ++nb) {
-          const int col = c0 + 16 * nb + (rr >> 1);
-          if (col >= s) continue;
-          Tf[2 * col + (rr & 1)] = acc[rt][nb][0][i] + acc[rt][nb][1][i];
-        }
-      }
+    for (int i = 0; i < 16; ++i) {
+      const int lr = 8 * (i / 4) + 4 * g + (i % 4);
+      if (lr >= item.rows || col >= s) continue;
+      bt[(bs.bt_off + dest[i]) * s16 + col] = make_float2(accR[i], accI[i]);
+    }
     return;
   }
   int x0, w, y0, hh;
   patch_box(sd.sx, sd.sy, bs.npx, bs.npy, item.patch, x0, w, y0, hh);
   const int bsz = w * hh;
   const bool final_plane = bwd || (k == sd.sz - 1);
-  float* Yk = reinterpret_cast<float*>(ybuf + (sd.y_off + (long long)k * sd.P) * s);
+  float2* Yk = ybuf + (sd.y_off + (long long)k * sd.P) * s;
+  const int colc = min(col, s - 1);
   // backward: x_k = y_k - (...): read every old value first (all loads in
   // flight together), then write
-  float old[RT][16][2];
+  float2 old[16];
 #pragma unroll
-  for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-    for (int i = 0; i < 16; ++i)
-#pragma unroll
-      for (int nb = 0; nb < 2; ++nb) old[rt][i][nb] = 0.f;
+  for (int i = 0; i < 16; ++i) old[i] = make_float2(0.f, 0.f);
   if (bwd) {
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int l = min(item.row0 + 32 * rt + 8 * (i / 4) + 4 * h + (i % 4), bsz - 1);
-        const float* yr = Yk + (long long)((y0 + l / w) * sd.sx + x0 + l % w) * 2 * s;
-#pragma unroll
-        for (int nb = 0; nb < 2; ++nb)
-          old[rt][i][nb] = yr[2 * min(c0 + 16 * nb + (rr >> 1), s - 1) + (rr & 1)];
-      }
+    for (int i = 0; i < 16; ++i) {
+      const int l = min(item.row0 + 8 * (i / 4) + 4 * g + (i % 4), bsz - 1);
+      old[i] = Yk[(long long)((y0 + l / w) * sd.sx + x0 + l % w) * s + colc];
+    }
   }
 #pragma unroll
-  for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int l = item.row0 + 32 * rt + 8 * (i / 4) + 4 * h + (i % 4);
-      if (l >= bsz) continue;
-      const int qx = x0 + l % w, qy = y0 + l / w;
-      float* yr = Yk + (long long)(qy * sd.sx + qx) * 2 * s;
-      long long zoff = -1;
-      if (final_plane) {
-        const int gx = sd.lo[0] + qx, gy = sd.lo[1] + qy, gz = sd.lo[2] + k;
-        if (gx >= sd.olo[0] && gx < sd.ohi[0] && gy >= sd.olo[1] && gy < sd.ohi[1] &&
-            gz >= sd.olo[2] && gz < sd.ohi[2])
-          zoff = (((long long)gz * ny + gy) * nx + gx) * s;
-      }
-#pragma unroll
-      for (int nb = 0; nb < 2; ++nb) {
-        const int col = c0 + 16 * nb + (rr >> 1);
-        if (col >= s) continue;
-        const int fi = 2 * col + (rr & 1);
-        float val = acc[rt][nb][0][i] + acc[rt][nb][1][i];
-        if (bwd) val = old[rt][i][nb] - val;
-        yr[fi] = val;
-        if (zoff >= 0) reinterpret_cast<ZR*>(z + zoff)[fi] = (ZR)val;
+  for (int i = 0; i < 16; ++i) {
+    const int l = item.row0 + 8 * (i / 4) + 4 * g + (i % 4);
+    if (l >= bsz || col >= s) continue;
+    const int qx = x0 + l % w, qy = y0 + l / w;
+    float2 val = make_float2(accR[i], accI[i]);
+    if (bwd) val = make_float2(old[i].x - val.x, old[i].y - val.y);
+    Yk[(long long)(qy * sd.sx + qx) * s + col] = val;
+    if (final_plane) {
+      const int gx = sd.lo[0] + qx, gy = sd.lo[1] + qy, gz = sd.lo[2] + k;
+      if (gx >= sd.olo[0] && gx < sd.ohi[0] && gy >= sd.olo[1] && gy < sd.ohi[1] &&
+          gz >= sd.olo[2] && gz < sd.ohi[2]) {
+        ZR* zr = reinterpret_cast<ZR*>(z + (((long long)gz * ny + gy) * nx + gx) * s + col);
+        zr[0] = (ZR)val.x;
+        zr[1] = (ZR)val.y;
       }
     }
+  }
 }
 
 // Complex FP64: 16x16x4 MFMA, RG groups of 16 rows x 16 columns per wave.
@@ -733,11 +713,11 @@ template <typename Z> struct BlrStep<float, Z> {
     if (ev) (void)hipEventRecord(ev[0], st);
     const int ncg = (s + 31) / 32;
     if (pl.p_count[k] > 0)
-      hipLaunchKernelGGL((blr_gemm_f32_kernel<1, 0, Z>), dim3((unsigned)(pl.p_count[k] * ncg)),
+      hipLaunchKernelGGL((blr_gemm_x3_kernel<0, Z>), dim3((unsigned)(pl.p_count[k] * ncg)),
                          dim3(64), 0, st, pl.subs, pl.bsubs, pl.items + pl.p_first[k],
                          pl.p_count[k], ncg, k, bwd, astore, pl.lists, bt, ybuf, z, nx, ny, s,
                          s16);
-    hipLaunchKernelGGL((blr_gemm_f32_kernel<1, 1, Z>), dim3((unsigned)(pl.e_count[k] * ncg)),
+    hipLaunchKernelGGL((blr_gemm_x3_kernel<1, Z>), dim3((unsigned)(pl.e_count[k] * ncg)),
                        dim3(64), 0, st, pl.subs, pl.bsubs, pl.items + pl.e_first[k],
                        pl.e_count[k], ncg, k, bwd, astore, pl.lists, bt, ybuf, z, nx, ny, s, s16);
     if (ev) (void)hipEventRecord(ev[1], st);
