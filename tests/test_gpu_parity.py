@@ -55,6 +55,8 @@ ORAS_CASES = [
     dict(n=(18, 16, 14), parts=(2, 2, 1), ov=2, npml=2, q=60.0, nrhs=20),
     dict(n=(15, 19, 13), parts=(1, 2, 2), ov=1, npml=2, q=None, nrhs=37),
     dict(n=(14, 14, 14), parts=(2, 2, 2), ov=2, npml=2, q=80.0, nrhs=64),
+    # 24 subdomains: the factorisation runs 8 and 16 of them on two streams
+    dict(n=(26, 23, 21), parts=(4, 3, 2), ov=2, npml=2, q=60.0, nrhs=5),
 ]
 
 
