@@ -78,7 +78,11 @@ def test_largest_subdomain_plane(prec):
     y = S.apply_M(b)
     r = b - S.apply_A(y, prec=oras.C128)
     res = float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(b))
-    assert res < (1e-10 if prec == 2 else 1e-3), res
+    say(f"  |b - A M^-1 b| / |b| = {res:.2e}")
+    # measured 4.9e-14 (FP64) and 1.5e-5 = 250 eps32 (FP32: the rounding of
+    # the plane inverses, amplified by the conditioning of A); the bars keep a
+    # factor of about 20 and 7
+    assert res < (1e-12 if prec == 2 else 1e-4), res
     sol = S.solve(b, 1e-6 if prec == 1 else 1e-10)
     assert sol.converged.all() and sol.total_iters <= (6 if prec == 1 else 1), sol.total_iters
     S.close()
