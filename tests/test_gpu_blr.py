@@ -7,8 +7,8 @@ import torch
 from oracle import blr as oblr, direct, operator as op, oras as ooras
 from paper_2110_15113_amd import workloads as wl
 
-from gpu_util import (BLR32_BOX, FP64_BOX, box_err, need_gpu, oracle_fields, rand_field, rel,
-                      say, setup, to_dev)
+from gpu_util import (BLR32_BOX, FP32_BOX, FP64_BOX, box_err, need_gpu, oracle_fields,
+                      rand_field, rel, say, setup, to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -62,6 +62,27 @@ def test_blr_eps_zero_is_the_dense_apply():
     S.factor(c["parts"], c["ov"], 2)
     again = S.apply_M(to_dev(x, S)).cpu().numpy()
     assert rel(again, dense) < 1e-14
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_blr_fp32_eps_zero_matches_exact_local_solves(case):
+    """With eps = 0 every block stays dense, so the complex-FP32 BLR products
+    (the expansion kernel over dense patch blocks in patch-major order) must
+    reproduce the exact local solves to the FP32 per-box bar."""
+    need_gpu()
+    w = wl.small_random(case["n"], npml=case["npml"], q=case["q"], seed=9,
+                        parts=case["parts"], overlap=case["ov"])
+    say(f"blr fp32 eps 0 {case}")
+    F = oracle_fields(w)
+    Md = ooras.ORAS(F, case["parts"], case["ov"])
+    S = setup(w, prec=1, parts=case["parts"], overlap=case["ov"])
+    info = S.compress(0.0, case["pmax"])
+    assert info["lowrank"] == 0, info
+    x = rand_field((w.nz, w.ny, w.nx), case["nrhs"], 6)
+    got = S.apply_M(to_dev(x, S)).cpu().numpy()
+    e = box_err(got, Md.apply(x), case["parts"], case["ov"])
+    say(f"  per-box error vs exact local solves {e:.2e}")
+    assert e < FP32_BOX, e
 
 
 @pytest.mark.parametrize("case", CASES)
