@@ -174,11 +174,11 @@ oras_status oras_set_m_ex(oras_ctx ctx, const double* m_dev, int flags);
  * z-planes of the box, explicit inverses of the plane Schur complements by
  * blocked Gauss-Jordan).  factor_prec: ORAS_C64 or ORAS_C128.  Each box must
  * have at least 2 nodes per axis and at most 8192 nodes per z-plane, and
- * overlap must be 0..8.  With 16 subdomains or more, half of them are
- * factored on a second stream that the context creates at default priority;
- * it is forked from and joined back into the context's stream inside the
- * call.  A zero or non-finite pivot returns ORAS_E_NUMERIC and leaves no
- * factors. */
+ * overlap must be 0..8.  With 16 subdomains or more, about half of them (a
+ * multiple of 8) are factored on a second stream that the context creates at
+ * default priority; it is forked from and joined back into the context's
+ * stream inside the call.  A zero or non-finite pivot returns ORAS_E_NUMERIC
+ * and leaves no factors. */
 oras_status oras_factor_subdomains(oras_ctx ctx, const int parts[3], int overlap,
                                    int factor_prec);
 
