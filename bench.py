@@ -392,7 +392,7 @@ def main():
         copy_probe(args.copy_probe)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1",
+        print(json.dumps({"error": "the solver runs on one GPU (subdomains are not sharded across GPUs); use --gpus 1",
                           "n_gpus": args.gpus}))
         sys.exit(1)
     if args.fwi and args.freqs > 1:
