@@ -503,6 +503,18 @@ def main():
                          "unit": "GB/s", "frac": round(gbps / PEAK["hbm_GBps"], 4),
                          "achieved_TFLOPs": round(ach, 2),
                          "fp32_equivalent_frac_of_fp32_mfma_peak": round(ach / peak, 4)})
+    rhs_rate = None
+    if not args.no_profile:
+        rs, rb = S.rhs_stats()
+        if rs > 0:
+            rhs_rate = {"kernel": ("blr_rhs" if args.blr is not None else "plane_rhs") +
+                        ("_f32_kernel" if args.blr is not None and P == oras.C64 else
+                         "_x3_kernel" if P == oras.C64 else "_f64_kernel") +
+                        " (restriction fused with the plane couplings)",
+                        "GBps": round(rb / rs / 1e9, 1),
+                        "hbm_frac": round(rb / rs / 1e9 / PEAK["hbm_GBps"], 4),
+                        "algorithmic_bytes_per_launch": rb / gl,
+                        "avg_launch_us": rs / gl * 1e6}
     rel_res = float(np.max(last.rel_res[:nrhs]))
     out = {
         "metric": "RHS solved/s to 1e-6 residual, mixed vs FP64 ORAS-FGMRES; 27-pt apply GB/s",
@@ -548,6 +560,9 @@ def main():
         if sten_TFLOPs else None,
         "dof_RHS_per_s": w.n * nrhs * args.steps / elapsed,
         "roofline": roof,
+        # the restriction R_j v runs fused into the plane right-hand-side
+        # kernel (and the prolongation into the products' epilogue)
+        "restrict_rhs": rhs_rate,
         # the paper's own figure for its pseudo-block ORAS solve, with the
         # hardware it names (another problem, machine and tolerance: context only)
         "paper_context": {"value": 0.506, "unit": "RHS/s", "dof_RHS_per_s": 67.5e6 * 0.506,

@@ -349,6 +349,18 @@ oras_status oras_profile(oras_ctx ctx, int enable);
 oras_status oras_kernel_stats(oras_ctx ctx, double* gemm_seconds, long long* gemm_launches,
                               double* gemm_flops, double* gemm_bytes);
 
+/* Accumulated time (s) and algorithmic bytes of the plane right-hand-side
+ * kernels, which carry the restriction R_j v of the ORAS apply (sec. 2.1)
+ * fused with the block couplings of the plane recursion (sec. 2.2), under
+ * the same oras_profile switch: per active subdomain plane of p nodes,
+ * p nrhs (16 (v, forward only) + b (neighbouring plane of y, except on the
+ * first forward plane) + t written) + 9 p b bytes of couplings, b the factor
+ * precision's bytes per complex value and t written as six bf16 pieces (12
+ * bytes) for the complex-FP32 dense products, else one value.  Each time is
+ * measured from the end of the previous plane step (or from the start of the
+ * apply) to the end of the kernel, so it includes one launch gap. */
+oras_status oras_rhs_stats(oras_ctx ctx, double* seconds, double* bytes);
+
 /* Copy the 27 FP64 stencil coefficients per node, layout (27, nz, ny, nx)
  * complex128, slot e = (ez+1)*9 + (ey+1)*3 + (ex+1). */
 oras_status oras_coefficients(oras_ctx ctx, void* out_dev);

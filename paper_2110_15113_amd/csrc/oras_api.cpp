@@ -117,6 +117,7 @@ struct oras_ctx_s {
   std::vector<hipEvent_t> gemm_ev;
   std::vector<double> plane_p2_fwd, plane_p2_bwd, plane_p_fwd, plane_p_bwd;
   double gemm_s = 0, gemm_flops = 0, gemm_bytes = 0;
+  double rhs_s = 0, rhs_bytes = 0;   // plane right-hand-side kernels (restriction fused)
   long long gemm_launches = 0;
 
   ~oras_ctx_s() {
@@ -395,14 +396,17 @@ oras_status oras_apply_internal(oras_ctx c, const double2* v, const double* scal
                                 bool z128, int nrhs) {
   TRY(ensure_oras_ws(c, s));
   const int nsteps = 2 * c->max_sz - 1;
+  // profiling: one event before the first plane step, then one after each
+  // step's right-hand-side kernel and one after its products
   hipEvent_t* ev = nullptr;
   if (c->prof) {
-    while ((int)c->gemm_ev.size() < 2 * nsteps) {
+    while ((int)c->gemm_ev.size() < 2 * nsteps + 1) {
       hipEvent_t e;
       HIP_TRY(c, hipEventCreate(&e));
       c->gemm_ev.push_back(e);
     }
-    ev = c->gemm_ev.data();
+    HIP_TRY(c, hipEventRecord(c->gemm_ev[0], c->stream));
+    ev = c->gemm_ev.data() + 1;
   }
   const OrasPlan& pl = c->plan;
   if (c->blr) {
@@ -449,13 +453,27 @@ oras_status oras_apply_internal(oras_ctx c, const double2* v, const double* scal
     // 8 p^2 nrhs flops; p^2 matrix entries + t read + y written (+ y read backward)
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     const double cs = (double)csize(c->factor_prec);
+    // right-hand side written: six bf16 pieces per FP32 complex value for the
+    // dense products, the plain value otherwise
+    const double tw = c->blr ? cs : (c->factor_prec == ORAS_C64 ? 12.0 : 16.0);
     for (int st = 0; st < nsteps; ++st) {
-      float ms = 0;
+      float ms = 0, mr = 0;
       HIP_TRY(c, hipEventElapsedTime(&ms, ev[2 * st], ev[2 * st + 1]));
+      HIP_TRY(c, hipEventElapsedTime(&mr, ev[2 * st - 1], ev[2 * st]));
       const bool bwd = st >= c->max_sz;
       const int k = bwd ? (c->max_sz - 2 - (st - c->max_sz)) : st;
       c->gemm_s += ms * 1e-3;
       c->gemm_launches += 1;
+      // right-hand side of each active plane: v restricted (forward, FP64),
+      // the neighbouring plane's y read (except forward plane 0), nine
+      // couplings per row, t written
+      {
+        const double p1 = bwd ? c->plane_p_bwd[k] : c->plane_p_fwd[k];
+        const bool couple = bwd || k > 0;
+        c->rhs_s += mr * 1e-3;
+        c->rhs_bytes += p1 * nrhs * ((bwd ? 0.0 : 16.0) + (couple ? cs : 0.0) + tw) +
+                        (couple ? 9.0 * p1 * cs : 0.0);
+      }
       if (c->blr) {
         // stored entries: 8 nrhs flops each; bytes: stored entries, gathered
         // rows and written rows (per right-hand side)
@@ -628,6 +646,14 @@ oras_status oras_profile(oras_ctx ctx, int enable) {
   ctx->prof = enable != 0;
   ctx->gemm_s = ctx->gemm_flops = ctx->gemm_bytes = 0;
   ctx->gemm_launches = 0;
+  ctx->rhs_s = ctx->rhs_bytes = 0;
+  return ORAS_OK;
+}
+
+oras_status oras_rhs_stats(oras_ctx ctx, double* seconds, double* bytes) {
+  if (!ctx) return ORAS_E_ARG;
+  if (seconds) *seconds = ctx->rhs_s;
+  if (bytes) *bytes = ctx->rhs_bytes;
   return ORAS_OK;
 }
 

@@ -106,6 +106,8 @@ SIGNATURES = {
     "oras_kernel_stats": (ct.c_int, [ct.c_void_p, ct.POINTER(ct.c_double),
                                      ct.POINTER(ct.c_longlong), ct.POINTER(ct.c_double),
                                      ct.POINTER(ct.c_double)]),
+    "oras_rhs_stats": (ct.c_int, [ct.c_void_p, ct.POINTER(ct.c_double),
+                                  ct.POINTER(ct.c_double)]),
     "oras_coefficients": (ct.c_int, [ct.c_void_p, ct.c_void_p]),
     "oras_subdomain": (ct.c_int, [ct.c_void_p, ct.c_int, ct.POINTER(ct.c_int),
                                   ct.POINTER(ct.c_int)]),
@@ -287,6 +289,13 @@ class Solver:
         self._check(lib().oras_kernel_stats(self._ctx, ct.byref(s), ct.byref(n), ct.byref(f),
                                             ct.byref(b)))
         return s.value, n.value, f.value, b.value
+
+    def rhs_stats(self):
+        """(seconds, algorithmic bytes) of the plane right-hand-side kernels
+        (restriction fused) since the last profile() call."""
+        s, b = ct.c_double(), ct.c_double()
+        self._check(lib().oras_rhs_stats(self._ctx, ct.byref(s), ct.byref(b)))
+        return s.value, b.value
 
     # -- solve -------------------------------------------------------------
     def solve(self, b: torch.Tensor, tol: float, restart: int = 30, maxit: int = 1000,

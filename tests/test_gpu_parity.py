@@ -279,6 +279,20 @@ def test_gemm_accounting(prec):
                 b += cs * (p * p + 3 * p * nrhs)
     assert flops == f and nbytes == b, (flops, f, nbytes, b)
     assert secs > 0
+    # the right-hand-side kernels (restriction fused): per active plane,
+    # p nrhs (16 forward + cs if coupled + t written) + 9 p cs if coupled,
+    # t as six bf16 pieces (12 bytes) in FP32, one value in FP64
+    rsecs, rbytes = S.rhs_stats()
+    tw = 12 if prec == 1 else 16
+    rb = 0.0
+    for s in subs:
+        p = (s.hi[0] - s.lo[0]) * (s.hi[1] - s.lo[1])
+        nz_ = s.hi[2] - s.lo[2]
+        for k in range(nz_):
+            rb += p * nrhs * (16 + (cs if k > 0 else 0) + tw) + (9 * p * cs if k > 0 else 0)
+            if k <= nz_ - 2 and k >= s.olo[2] - s.lo[2]:
+                rb += p * nrhs * (cs + tw) + 9 * p * cs
+    assert rbytes == rb and rsecs > 0, (rbytes, rb, rsecs)
 
 
 PIVOT_CASES = [
