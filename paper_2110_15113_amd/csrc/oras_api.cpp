@@ -908,11 +908,9 @@ oras_status oras_factor_subdomains_ex(oras_ctx c, const int parts[3], int overla
   const int nh = nsub >= 16 ? nsub / 16 * 8 : nsub;
   const int nparts = nh < nsub ? 2 : 1;
   if (nparts == 2) {
-    if (!c->stream2) {
-      HIP_TRY(c, hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking));
-      HIP_TRY(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
-      HIP_TRY(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
-    }
+    if (!c->stream2) HIP_TRY(c, hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking));
+    if (!c->ev_fork) HIP_TRY(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+    if (!c->ev_join) HIP_TRY(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
     HIP_TRY(c, hipEventRecord(c->ev_fork, c->stream));
     HIP_TRY(c, hipStreamWaitEvent(c->stream2, c->ev_fork, 0));
   }
