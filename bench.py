@@ -453,20 +453,21 @@ def main():
     last, ta, tf = results[-1]
     ok = bool(last.converged.all())
     iters = int(last.total_iters)
-    # 27-point apply against its algorithmic bytes: x read in the stencil
-    # precision, y written in complex128 (the Arnoldi basis), and the node
-    # fields the operator is formed from (three mass weights and the complex
-    # squared slowness in the stencil precision, five values per node; the
-    # stiffness needs only the 1D PML profiles).  Its arithmetic floor: one
-    # complex multiply-add (four real FMAs, 8 flops) per node, neighbour and
-    # right-hand side on the vector ALUs.
-    cb = 8 if P == oras.C64 else 16
+    # 27-point apply of the Arnoldi step against its algorithmic bytes: x read
+    # and y written in the precision A z_j runs in (a single-precision y is
+    # widened by Gram-Schmidt), and the node fields the operator is formed
+    # from (three mass weights and the complex squared slowness, five values
+    # per node; the stiffness needs only the 1D PML profiles).  Its arithmetic
+    # floor: one complex multiply-add (four real FMAs, 8 flops) per node,
+    # neighbour and right-hand side on the vector ALUs.
+    k64 = (kp or P) == oras.C64
+    cb = 8 if k64 else 16
     s_pad = (nrhs + 7) // 8 * 8
-    sten_bytes = w.n * (s_pad * (cb + 16) + 5 * (cb // 2))
+    sten_bytes = w.n * (s_pad * (cb + cb) + 5 * (cb // 2))
     sten_flops = w.n * s_pad * 27 * 8
     sten_GBps = sten_bytes * iters / last.t_stencil / 1e9 if last.t_stencil > 0 else None
     sten_TFLOPs = sten_flops * iters / last.t_stencil / 1e12 if last.t_stencil > 0 else None
-    vec_peak = PEAK["fp32_vector_TFLOPs"] if P == oras.C64 else PEAK["fp64_vector_TFLOPs"]
+    vec_peak = PEAK["fp32_vector_TFLOPs"] if k64 else PEAK["fp64_vector_TFLOPs"]
     roof = None
     if not args.no_profile:
         gs, gl, gf, gb = S.kernel_stats()

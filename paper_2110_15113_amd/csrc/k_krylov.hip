@@ -126,9 +126,15 @@ __global__ void __launch_bounds__(256) finish_norm_kernel(const double* __restri
   if (threadIdx.x == 0) out[c] = sqrt(t);
 }
 
-// partial[blk][i][c] = sum_nodes conj(V_i) w   for i < j1   (scale applied later)
+__device__ inline double2 as_c128(double2 v) { return v; }
+__device__ inline double2 as_c128(float2 v) { return make_double2((double)v.x, (double)v.y); }
+
+// partial[blk][i][c] = sum_nodes conj(V_i) w   for i < j1   (scale applied later).
+// w is complex128, or complex64 when it comes from the single-precision
+// stencil (whose values are FP32 ones: widening them is exact).
+template <typename W>
 __global__ void cgs_dot_kernel(const double2* __restrict__ V, long long vstride, int j1,
-                               const double2* __restrict__ w, long long n, int s,
+                               const W* __restrict__ w, long long n, int s,
                                double2* __restrict__ partial) {
   __shared__ double lre[8 * 256];
   __shared__ double lim[8 * 256];
@@ -141,7 +147,7 @@ __global__ void cgs_dot_kernel(const double2* __restrict__ V, long long vstride,
     for (int ii = 0; ii < 8; ++ii) acc[ii] = make_double2(0.0, 0.0);
     for (long long node = (long long)blockIdx.x * G + g; node < n;
          node += (long long)gridDim.x * G) {
-      const double2 wv = w[node * s + c];
+      const double2 wv = as_c128(w[node * s + c]);
 #pragma unroll
       for (int ii = 0; ii < 8; ++ii)
         if (ii < cnt) cfmaconj(acc[ii], ldnt2(&V[(long long)(i0 + ii) * vstride + node * s + c]), wv);
@@ -209,22 +215,25 @@ cgs_finish_dot_kernel(const double2* __restrict__ partial, int nblk, int j1, int
   }
 }
 
-// w -= sum_i V_i hs_i ; partial[blk][c] = sum |w|^2
+// wout = win - sum_i V_i hs_i (complex128; win complex128 in place, or the
+// complex64 output of the single-precision stencil); partial[blk][c] = sum |wout|^2
+template <typename W>
 __global__ void cgs_update_kernel(const double2* __restrict__ V, long long vstride, int j1,
-                                  const double2* __restrict__ hs, double2* __restrict__ w,
-                                  long long n, int s, double* __restrict__ partial) {
+                                  const double2* __restrict__ hs, const W* win,
+                                  double2* wout, long long n, int s,
+                                  double* __restrict__ partial) {
   __shared__ double lds[256];
   const int G = blockDim.x / s;
   const int c = threadIdx.x % s, g = threadIdx.x / s;
   double acc = 0.0;
   for (long long node = (long long)blockIdx.x * G + g; node < n; node += (long long)gridDim.x * G) {
-    double2 wv = w[node * s + c];
+    double2 wv = as_c128(win[node * s + c]);
     for (int i = 0; i < j1; ++i) {
       const double2 v = ldnt2(&V[(long long)i * vstride + node * s + c]);
       const double2 hh = hs[i * s + c];
       cfms(wv, v, hh);
     }
-    stnt2(&w[node * s + c], wv);
+    stnt2(&wout[node * s + c], wv);
     acc += wv.x * wv.x + wv.y * wv.y;
   }
   block_reduce_store(lds, acc, s, G, partial + (long long)blockIdx.x * s + c);
@@ -467,21 +476,34 @@ void launch_colnorm2(const double2* x, long long n, int s, double* partial, int 
 void launch_finish_norm(const double* partial, int nblk, int s, double* out, hipStream_t st) {
   hipLaunchKernelGGL(finish_norm_kernel, dim3(s), dim3(256), 0, st, partial, nblk, s, out);
 }
-void launch_cgs_dot(const double2* V, long long vstride, int j1, const double2* w, long long n,
-                    int s, double2* partial, int nblk, hipStream_t st) {
-  hipLaunchKernelGGL(cgs_dot_kernel, dim3(nblk), dim3(group_threads(s)), 0, st, V, vstride, j1, w,
-                     n, s, partial);
+template <typename W>
+void launch_cgs_dot(const double2* V, long long vstride, int j1, const W* w, long long n, int s,
+                    double2* partial, int nblk, hipStream_t st) {
+  hipLaunchKernelGGL((cgs_dot_kernel<W>), dim3(nblk), dim3(group_threads(s)), 0, st, V, vstride,
+                     j1, w, n, s, partial);
 }
+template void launch_cgs_dot<double2>(const double2*, long long, int, const double2*, long long,
+                                      int, double2*, int, hipStream_t);
+template void launch_cgs_dot<float2>(const double2*, long long, int, const float2*, long long,
+                                     int, double2*, int, hipStream_t);
 void launch_cgs_finish_dot(const double2* partial, int nblk, int j1, int s, const double* scale,
                            double2* h, double2* hs, hipStream_t st) {
   hipLaunchKernelGGL(cgs_finish_dot_kernel, dim3(j1 * s), dim3(256), 0, st, partial, nblk, j1, s,
                      scale, h, hs);
 }
-void launch_cgs_update(const double2* V, long long vstride, int j1, const double2* hs, double2* w,
-                       long long n, int s, double* partial, int nblk, hipStream_t st) {
-  hipLaunchKernelGGL(cgs_update_kernel, dim3(nblk), dim3(group_threads(s)), 0, st, V, vstride, j1,
-                     hs, w, n, s, partial);
+template <typename W>
+void launch_cgs_update(const double2* V, long long vstride, int j1, const double2* hs,
+                       const W* win, double2* wout, long long n, int s, double* partial, int nblk,
+                       hipStream_t st) {
+  hipLaunchKernelGGL((cgs_update_kernel<W>), dim3(nblk), dim3(group_threads(s)), 0, st, V,
+                     vstride, j1, hs, win, wout, n, s, partial);
 }
+template void launch_cgs_update<double2>(const double2*, long long, int, const double2*,
+                                         const double2*, double2*, long long, int, double*, int,
+                                         hipStream_t);
+template void launch_cgs_update<float2>(const double2*, long long, int, const double2*,
+                                        const float2*, double2*, long long, int, double*, int,
+                                        hipStream_t);
 void launch_arnoldi_step(int j, int m, int s, const double* hnorm, const double2* h, double2* H,
                          double* cs, double2* sn, double2* g, double* scale_next, int* jc,
                          int* done, const double* bnorm, double tol, double* est,

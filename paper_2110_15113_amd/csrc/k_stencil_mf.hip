@@ -121,10 +121,10 @@ enum { FIRST = 0, MID = 1, LAST = 2 };
 
 // PML: tiles the PML reaches (profile factors formed), else PML-free tiles.
 // RC: right-hand sides of the work-group's chunk (a multiple of 8).
-template <typename R, bool PML, int RC>
+template <typename R, bool PML, int RC, typename Y>
 __global__ void __launch_bounds__(NTHREADS)
 stencil_mf_kernel(StencilMF<R> op, const int4* __restrict__ tiles, const C<R>* __restrict__ x,
-                  const double2* __restrict__ b, double2* __restrict__ y, int nx, int ny, int nz,
+                  const double2* __restrict__ b, Y* __restrict__ y, int nx, int ny, int nz,
                   int s, int c_first, int nitems, int per_xcd, int nchunk) {
   using T = C<R>;
   using V4 = typename R4<R>::type;
@@ -335,7 +335,12 @@ stencil_mf_kernel(StencilMF<R> op, const int4* __restrict__ tiles, const C<R>* _
       for (int q = 0; q < RT; ++q) {
         double2 out = make_double2((double)acc[0][q].x, (double)acc[0][q].y);
         if (b) out = csub(b[o + q], out);
-        y[o + q] = out;
+        if constexpr (std::is_same<Y, double2>::value) {
+          y[o + q] = out;
+        } else {
+          // single-precision output (no b): the value is already an FP32 one
+          y[o + q] = make_float2((float)out.x, (float)out.y);
+        }
       }
     }
 #pragma unroll
@@ -390,35 +395,35 @@ __global__ void mass_fields_kernel(const double* w7, const double2* mt, long lon
   fim[i] = (R)mt[i].y;
 }
 
-template <typename R, bool PML, int RC>
-void launch_chunks(const StencilMF<R>& op, const C<R>* x, const double2* b, double2* y, int nx,
+template <typename R, bool PML, int RC, typename Y>
+void launch_chunks(const StencilMF<R>& op, const C<R>* x, const double2* b, Y* y, int nx,
                    int ny, int nz, int s, int c_first, int nchunk, hipStream_t st) {
   const int lo = PML ? op.nplain : 0, hi = PML ? op.ntiles : op.nplain;
   if (hi == lo || nchunk == 0) return;
   const int nitems = (hi - lo) * nchunk;
   const int per_xcd = (nitems + NXCD - 1) / NXCD;
-  hipLaunchKernelGGL((stencil_mf_kernel<R, PML, RC>), dim3((unsigned)(per_xcd * NXCD)),
+  hipLaunchKernelGGL((stencil_mf_kernel<R, PML, RC, Y>), dim3((unsigned)(per_xcd * NXCD)),
                      dim3(NTHREADS), 0, st, op, op.tiles + lo, x, b, y, nx, ny, nz, s, c_first,
                      nitems, per_xcd, nchunk);
 }
 
-template <typename R, bool PML>
-void launch_kind(const StencilMF<R>& op, const C<R>* x, const double2* b, double2* y, int nx,
+template <typename R, bool PML, typename Y>
+void launch_kind(const StencilMF<R>& op, const C<R>* x, const double2* b, Y* y, int nx,
                  int ny, int nz, int s, hipStream_t st) {
   // chunks of the widest width, then narrower chunks for the rest (s is a
   // multiple of 8)
   constexpr int RC = MfChunk<R, PML>::RC;
   const int full = s / RC;
   int c = full * RC;
-  launch_chunks<R, PML, RC>(op, x, b, y, nx, ny, nz, s, 0, full, st);
+  launch_chunks<R, PML, RC, Y>(op, x, b, y, nx, ny, nz, s, 0, full, st);
   if constexpr (RC > 16) {
     if (s - c >= 16) {
-      launch_chunks<R, PML, 16>(op, x, b, y, nx, ny, nz, s, c, 1, st);
+      launch_chunks<R, PML, 16, Y>(op, x, b, y, nx, ny, nz, s, c, 1, st);
       c += 16;
     }
   }
   if constexpr (RC > 8) {
-    if (s - c >= 8) launch_chunks<R, PML, 8>(op, x, b, y, nx, ny, nz, s, c, 1, st);
+    if (s - c >= 8) launch_chunks<R, PML, 8, Y>(op, x, b, y, nx, ny, nz, s, c, 1, st);
   }
 }
 
@@ -451,21 +456,26 @@ void stencil_mf_tiles(const int lo[3], const int hi[3], int nx, int ny, int nz,
   tiles.insert(tiles.end(), pml.begin(), pml.end());
 }
 
-template <typename R>
-void launch_stencil_mf(const StencilMF<R>& op, const C<R>* x, const double2* b, double2* y, int nx,
+template <typename R, typename Y>
+void launch_stencil_mf(const StencilMF<R>& op, const C<R>* x, const double2* b, Y* y, int nx,
                        int ny, int nz, int s, hipStream_t st) {
   static_assert(RHS_ALIGN == 8, "chunk widths cover multiples of 8");
-  launch_kind<R, false>(op, x, b, y, nx, ny, nz, s, st);
-  launch_kind<R, true>(op, x, b, y, nx, ny, nz, s, st);
+  launch_kind<R, false, Y>(op, x, b, y, nx, ny, nz, s, st);
+  launch_kind<R, true, Y>(op, x, b, y, nx, ny, nz, s, st);
 }
 
 template void launch_mass_fields<float>(const double*, const double2*, long long, float4*, float*,
                                         hipStream_t);
 template void launch_mass_fields<double>(const double*, const double2*, long long, double4*,
                                          double*, hipStream_t);
-template void launch_stencil_mf<float>(const StencilMF<float>&, const float2*, const double2*,
-                                       double2*, int, int, int, int, hipStream_t);
-template void launch_stencil_mf<double>(const StencilMF<double>&, const double2*, const double2*,
-                                        double2*, int, int, int, int, hipStream_t);
+template void launch_stencil_mf<float, double2>(const StencilMF<float>&, const float2*,
+                                                const double2*, double2*, int, int, int, int,
+                                                hipStream_t);
+template void launch_stencil_mf<float, float2>(const StencilMF<float>&, const float2*,
+                                               const double2*, float2*, int, int, int, int,
+                                               hipStream_t);
+template void launch_stencil_mf<double, double2>(const StencilMF<double>&, const double2*,
+                                                 const double2*, double2*, int, int, int, int,
+                                                 hipStream_t);
 
 }  // namespace oras

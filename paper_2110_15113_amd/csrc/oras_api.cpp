@@ -108,7 +108,7 @@ struct oras_ctx_s {
   oras_blr_info blr_info{};
 
   // per-solve workspace (grown on demand)
-  DevBuf ybuf, tvbuf, V, Z, Bint, Xint, Tmp, Tmp64, partial, small;
+  DevBuf ybuf, tvbuf, V, Z, Bint, Xint, Tmp, Tmp64, W32, partial, small;
   long long ws_s = 0;
   int ws_m = 0;
 
@@ -152,6 +152,7 @@ struct oras_ctx_s {
   }
   void release_workspace() {
     V.release(); Z.release(); Bint.release(); Xint.release(); Tmp.release(); Tmp64.release();
+    W32.release();
     partial.release(); small.release();
     ws_s = 0;
     ws_m = 0;
@@ -344,10 +345,10 @@ template <> StencilMF<float> mf_view<float>(oras_ctx c) {
   return v;
 }
 
-// y (internal [n][s] c128) = A x, or b - A x when b is given, with x in the
-// stencil precision R
-template <typename R>
-void apply_stencil(oras_ctx c, const C<R>* x, const double2* b, double2* y, int s, hipStream_t st) {
+// y (internal [n][s], c128 or, in single precision without b, c64) = A x, or
+// b - A x when b is given, with x in the stencil precision R
+template <typename R, typename Y = double2>
+void apply_stencil(oras_ctx c, const C<R>* x, const double2* b, Y* y, int s, hipStream_t st) {
   StencilMF<R> v = mf_view<R>(c);
   v.fy = v.fx + 9 * c->nx;
   v.fz = v.fy + 9 * c->ny;
@@ -362,7 +363,7 @@ void apply_stencil(oras_ctx c, const C<R>* x, const double2* b, double2* y, int 
   v.W2 = t.w[1] * ih2 * 0.125;
   v.W3 = t.w[2] * ih2 * 0.0625;
   v.om2 = c->omega * c->omega;
-  launch_stencil_mf<R>(v, x, b, y, c->nx, c->ny, c->nz, s, st);
+  launch_stencil_mf<R, Y>(v, x, b, y, c->nx, c->ny, c->nz, s, st);
 }
 
 int nblk_for(long long n) {
@@ -1424,6 +1425,7 @@ oras_status oras_solve(oras_ctx c, const void* b_dev, void* x_dev, int nrhs, dou
   {
     double need = 0;
     if (!c->V.p || c->ws_s < s || c->ws_m < m) need += (double)ns * ((m + 1) * 16.0 + m * zsz + 2 * 16.0);
+    if (kprec == ORAS_C64 && c->W32.bytes < (size_t)ns * sizeof(float2)) need += (double)ns * 8.0;
     if (convert) {
       const DevBuf& tb = kprec == ORAS_C64 ? c->Tmp64 : c->Tmp;
       const size_t tbytes = (size_t)ns * (kprec == ORAS_C64 ? sizeof(float2) : sizeof(double2));
@@ -1440,6 +1442,9 @@ oras_status oras_solve(oras_ctx c, const void* b_dev, void* x_dev, int nrhs, dou
   TRY(dev_alloc(c, c->Z, (size_t)(m * ns) * zsz));
   TRY(dev_alloc(c, c->Bint, (size_t)ns * sizeof(double2)));
   TRY(dev_alloc(c, c->Xint, (size_t)ns * sizeof(double2)));
+  // A z_j from the single-precision stencil lands in complex64 (its values
+  // are FP32 ones); Gram-Schmidt widens it and writes v_{j+1} in complex128
+  if (kprec == ORAS_C64) TRY(dev_alloc(c, c->W32, (size_t)ns * sizeof(float2)));
   TRY(dev_alloc(c, c->partial, (size_t)nblk * (m + 1) * s * sizeof(double2)));
   // small per-column state
   const size_t sH = (size_t)(m + 1) * m * s, sG = (size_t)(m + 1) * s;
@@ -1525,7 +1530,7 @@ oras_status oras_solve(oras_ctx c, const void* b_dev, void* x_dev, int nrhs, dou
           launch_cast<float>((const double2*)Zj, c->Tmp64.as<float2>(), ns, st);
           zin = c->Tmp64.as<float2>();
         }
-        apply_stencil<float>(c, zin, nullptr, Vn, (int)s, st);
+        apply_stencil<float, float2>(c, zin, nullptr, c->W32.as<float2>(), (int)s, st);
       } else {
         const double2* zin = (const double2*)Zj;
         if (convert) {
@@ -1535,9 +1540,16 @@ oras_status oras_solve(oras_ctx c, const void* b_dev, void* x_dev, int nrhs, dou
         apply_stencil<double>(c, zin, nullptr, Vn, (int)s, st);
       }
       HIP_TRY(c, hipEventRecord(ev[2], st));
-      launch_cgs_dot(V, ns, j + 1, Vn, n, (int)s, dpart, nblk, st);
-      launch_cgs_finish_dot(dpart, nblk, j + 1, (int)s, scale, hv, hs, st);
-      launch_cgs_update(V, ns, j + 1, hs, Vn, n, (int)s, npart, nblk, st);
+      if (kprec == ORAS_C64) {
+        const float2* w32 = c->W32.as<float2>();
+        launch_cgs_dot(V, ns, j + 1, w32, n, (int)s, dpart, nblk, st);
+        launch_cgs_finish_dot(dpart, nblk, j + 1, (int)s, scale, hv, hs, st);
+        launch_cgs_update(V, ns, j + 1, hs, w32, Vn, n, (int)s, npart, nblk, st);
+      } else {
+        launch_cgs_dot(V, ns, j + 1, (const double2*)Vn, n, (int)s, dpart, nblk, st);
+        launch_cgs_finish_dot(dpart, nblk, j + 1, (int)s, scale, hv, hs, st);
+        launch_cgs_update(V, ns, j + 1, hs, (const double2*)Vn, Vn, n, (int)s, npart, nblk, st);
+      }
       launch_finish_norm(npart, nblk, (int)s, hnorm, st);
       launch_arnoldi_step(j, m, (int)s, hnorm, hv, H, cs, sn, g, scale + (j + 1) * s, jc, done,
                           bnorm, tol, est, st);

@@ -191,8 +191,10 @@ void launch_mass_fields(const double* w7, const double2* mt, long long n,
 // uses are 1), then the PML tiles covering the rest of the grid.
 void stencil_mf_tiles(const int lo[3], const int hi[3], int nx, int ny, int nz,
                       std::vector<int>& tiles, int& nplain);
-template <typename R>
-void launch_stencil_mf(const StencilMF<R>& op, const C<R>* x, const double2* b, double2* y, int nx,
+// y = A x (or b - A x) in [n][s] layout; y is complex128, or complex64 for
+// the single-precision apply without b (its values are FP32 ones either way).
+template <typename R, typename Y = double2>
+void launch_stencil_mf(const StencilMF<R>& op, const C<R>* x, const double2* b, Y* y, int nx,
                        int ny, int nz, int s, hipStream_t st);
 
 
@@ -229,12 +231,15 @@ void launch_from_internal(const double2* src, double2* dst, long long n, int nrh
                           hipStream_t st);
 void launch_colnorm2(const double2* x, long long n, int s, double* partial, int nblk, hipStream_t st);
 void launch_finish_norm(const double* partial, int nblk, int s, double* out, hipStream_t st);
-void launch_cgs_dot(const double2* V, long long vstride, int j1, const double2* w, long long n,
-                    int s, double2* partial, int nblk, hipStream_t st);
+template <typename W>
+void launch_cgs_dot(const double2* V, long long vstride, int j1, const W* w, long long n, int s,
+                    double2* partial, int nblk, hipStream_t st);
 void launch_cgs_finish_dot(const double2* partial, int nblk, int j1, int s, const double* scale,
                            double2* h, double2* hs, hipStream_t st);
-void launch_cgs_update(const double2* V, long long vstride, int j1, const double2* hs, double2* w,
-                       long long n, int s, double* partial, int nblk, hipStream_t st);
+template <typename W>
+void launch_cgs_update(const double2* V, long long vstride, int j1, const double2* hs,
+                       const W* win, double2* wout, long long n, int s, double* partial, int nblk,
+                       hipStream_t st);
 void launch_arnoldi_step(int j, int m, int s, const double* hnorm, const double2* h, double2* H,
                          double* cs, double2* sn, double2* g, double* scale_next, int* jc,
                          int* done, const double* bnorm, double tol, double* est,
