@@ -28,15 +28,33 @@ __global__ void to_internal_kernel(const double2* __restrict__ src, double2* __r
   dst[idx] = v;
 }
 
-__global__ void from_internal_kernel(const double2* __restrict__ src, double2* __restrict__ dst,
-                                     long long n, int nrhs, int s, int conj) {
-  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= n * (long long)nrhs) return;
-  const int c = (int)(idx / n);
-  const long long node = idx % n;
-  double2 v = src[node * s + c];
-  if (conj) v.y = -v.y;
-  dst[idx] = v;
+// [n][s] -> [nrhs][n] through an LDS tile of 64 nodes x 32 columns, so that
+// both the reads (a node's columns) and the writes (a column's nodes) are
+// contiguous runs.
+constexpr int TR_NODES = 64, TR_COLS = 32;
+__global__ void __launch_bounds__(256)
+from_internal_kernel(const double2* __restrict__ src, double2* __restrict__ dst, long long n,
+                     int nrhs, int s, int conj) {
+  __shared__ double2 tile[TR_NODES][TR_COLS + 1];
+  const long long node0 = (long long)blockIdx.x * TR_NODES;
+  const int c0 = blockIdx.y * TR_COLS;
+  for (int i = threadIdx.x; i < TR_NODES * TR_COLS; i += 256) {
+    const int r = i / TR_COLS, j = i % TR_COLS;
+    const long long node = node0 + r;
+    const int c = c0 + j;
+    if (node < n && c < nrhs) tile[r][j] = src[node * s + c];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < TR_NODES * TR_COLS; i += 256) {
+    const int j = i / TR_NODES, r = i % TR_NODES;
+    const long long node = node0 + r;
+    const int c = c0 + j;
+    if (node < n && c < nrhs) {
+      double2 v = tile[r][j];
+      if (conj) v.y = -v.y;
+      dst[(long long)c * n + node] = v;
+    }
+  }
 }
 
 // Sum over the lanes of a 64-lane wave that share lane % s (s a power of
@@ -466,8 +484,9 @@ void launch_to_internal(const double2* src, double2* dst, long long n, int nrhs,
 }
 void launch_from_internal(const double2* src, double2* dst, long long n, int nrhs, int s, int conj,
                           hipStream_t st) {
-  hipLaunchKernelGGL(from_internal_kernel, dim3(blocks_for(n * nrhs, 256)), dim3(256), 0, st, src,
-                     dst, n, nrhs, s, conj);
+  const dim3 grid((unsigned)((n + TR_NODES - 1) / TR_NODES),
+                  (unsigned)((nrhs + TR_COLS - 1) / TR_COLS));
+  hipLaunchKernelGGL(from_internal_kernel, grid, dim3(256), 0, st, src, dst, n, nrhs, s, conj);
 }
 void launch_colnorm2(const double2* x, long long n, int s, double* partial, int nblk,
                      hipStream_t st) {
